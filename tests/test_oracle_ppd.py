@@ -1,0 +1,162 @@
+"""Pins for the FP64 Algorithm 3 oracle and the problem assembly."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import nufft as nf
+from oracle import ppd as O
+from oracle import problem as P
+from oracle import prox, sara
+
+
+@pytest.fixture(scope="module")
+def small():
+    """A 32x32 problem with 3 radial blocks, built with a short power iteration."""
+    x, wu, wv, off = synth.small_case(32, 3000, seed=11, d=3)
+    noise = synth.noise_unit(wu.size, 211)
+    pb = P.make_problem(x, wu, wv, off, noise, 30.0, np.ones((32, 32)), power_tol=1e-9)
+    return pb
+
+
+def _params(pb, U, eta, n_itr=1):
+    return O.Params(eta=eta, mu=1.0 / U.max(), n_itr=n_itr)
+
+
+def test_first_iteration_closed_form(small):
+    pb = small
+    prm = _params(pb, pb.U, pb.eta, n_itr=1)
+    st = O.init_state(32, 32, pb.y)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, st, 1)
+    # from zeros: z = P_B((1 - mu U) y) per block, v = -U z, u = 0,
+    # x = max(0, tau eta Re Phi^H (U z)), x tilde = 2 x
+    z = np.empty_like(pb.y)
+    for j in range(len(pb.eps)):
+        s = slice(pb.block_off[j], pb.block_off[j + 1])
+        z[s] = prox.proj_B((1 - prm.mu * pb.U[s]) * pb.y[s], pb.y[s], pb.eps[j])
+    x1 = np.maximum(prm.tau * prm.eta * pb.op.phit(pb.U * z), 0.0)
+    assert np.allclose(st.z, z, rtol=1e-13, atol=0)
+    assert np.allclose(st.v, -pb.U * z, rtol=1e-13, atol=0)
+    assert np.abs(st.u).max() == 0.0
+    assert np.abs(st.x - x1).max() <= 1e-13 * np.abs(x1).max()
+    assert np.abs(st.xt - 2 * x1).max() <= 1e-13 * np.abs(x1).max()
+
+
+def _pd_reference(pb, eta, T, lam=1.0):
+    """Non-preconditioned PD written independently: vbar = w - P_B(w)."""
+    op = pb.op
+    ny, nx = pb.x_true.shape
+    x = np.zeros((ny, nx)); xt = np.zeros((ny, nx))
+    v = np.zeros(pb.y.size, complex); u = np.zeros((9, ny, nx))
+    for _ in range(T):
+        g = op.phi(xt)
+        for j in range(len(pb.eps)):
+            s = slice(pb.block_off[j], pb.block_off[j + 1])
+            w = v[s] + g[s]
+            v[s] = (1 - lam) * v[s] + lam * (w - prox.proj_B(w, pb.y[s], pb.eps[j]))
+        u = (1 - lam) * u + lam * np.clip(u + sara.analysis(xt), -1e-4, 1e-4)
+        xb = np.maximum(x - 0.49 * (eta * op.phit(v) + sara.synthesis(u)), 0.0)
+        xt = 2 * xb - x
+        x = (1 - lam) * x + lam * xb
+    return x
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.7])
+def test_identity_preconditioner_gives_pd(small, lam):
+    pb = small
+    U = np.ones_like(pb.U)
+    st = O.init_state(32, 32, pb.y)
+    prm = _params(pb, U, pb.eta_pd)
+    prm.lam = lam
+    O.iterate(pb.op, pb.y, U, pb.eps, pb.block_off, prm, st, 8)
+    xr = _pd_reference(pb, pb.eta_pd, 8, lam)
+    assert np.abs(st.x - xr).max() <= 1e-11 * np.abs(xr).max()
+
+
+def test_preconditioner_scale_invariance(small):
+    pb = small
+    a = O.init_state(32, 32, pb.y)
+    b = O.init_state(32, 32, pb.y)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, _params(pb, pb.U, pb.eta, 2), a, 6)
+    U2 = 2.0 * pb.U
+    O.iterate(pb.op, pb.y, U2, pb.eps, pb.block_off, _params(pb, U2, pb.eta / 2.0, 2), b, 6)
+    assert np.array_equal(a.x, b.x)          # power-of-2 scaling: bitwise
+    assert np.array_equal(2.0 * a.v, b.v)
+
+
+def test_resume_is_bitwise(small):
+    pb = small
+    prm = _params(pb, pb.U, pb.eta, 2)
+    a = O.init_state(32, 32, pb.y)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, a, 6)
+    b = O.init_state(32, 32, pb.y)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, b, 3)
+    c = b.copy()
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, c, 3)
+    assert np.array_equal(a.x, c.x) and np.array_equal(a.v, c.v) and np.array_equal(a.u, c.u)
+
+
+def test_ppd_and_pd_converge_on_workload():
+    inp = synth.make_inputs(synth.WORKLOADS["ppd64"])
+    pb = P.problem_from_inputs(inp, power_tol=1e-8)
+    out = {}
+    for name, U, eta in [("ppd", pb.U, pb.eta), ("pd", np.ones_like(pb.U), pb.eta_pd)]:
+        st = O.init_state(64, 64, pb.y)
+        h = O.iterate(pb.op, pb.y, U, pb.eps, pb.block_off, _params(pb, U, eta), st, 150,
+                      x_true=pb.x_true)
+        out[name] = h
+        assert h[-1]["snr"] > 15.0
+        assert h[-1]["snr"] > h[9]["snr"]
+        assert h[-1]["residual"][0] <= 1.05 * pb.eps[0]
+        assert np.all(st.x >= 0)
+    # both approach the same solution of the same problem
+    assert abs(out["ppd"][-1]["snr"] - out["pd"][-1]["snr"]) < 1.5
+
+
+def test_uniform_weights_brute_force():
+    rng = np.random.default_rng(3)
+    M, ny, nx = 500, 8, 16
+    wu = rng.uniform(-math.pi, math.pi, M).astype(np.float32)
+    wv = (rng.standard_normal(M) * 0.5).clip(-3.14, 3.14).astype(np.float32)
+    U = P.uniform_weights(wu, wv, ny, nx)
+    cu = [min(nx - 1, int(math.floor((float(a) + math.pi) * nx / (2 * math.pi)))) for a in wu]
+    cv = [min(ny - 1, int(math.floor((float(b) + math.pi) * ny / (2 * math.pi)))) for b in wv]
+    counts = {}
+    for k in zip(cv, cu):
+        counts[k] = counts.get(k, 0) + 1
+    c = np.array([counts[k] for k in zip(cv, cu)], dtype=float)
+    assert np.array_equal(U, c.min() / c)
+    assert U.max() == 1.0 and U.min() > 0
+
+
+def test_power_norm_matches_dense_eigenvalue():
+    x, wu, wv, _ = synth.small_case(8, 120, seed=13)
+    op = nf.Nufft(wu, wv, 8, 8)
+    U = P.uniform_weights(wu, wv, 8, 8)
+    A = np.empty((64, 64))
+    for k in range(64):
+        e = np.zeros(64); e[k] = 1
+        A[:, k] = op.phit(U * op.phi(e.reshape(8, 8))).ravel()
+    lam = np.linalg.eigvalsh(0.5 * (A + A.T)).max()
+    assert P.power_norm(op, U, np.ones((8, 8)), tol=1e-13, max_iter=5000) == pytest.approx(lam, rel=1e-9)
+
+
+def test_l2_bound_is_chi_square_mean_plus_two_std():
+    # ||n_j||^2 / sigma^2 ~ chi^2_{2 M_j} / 2: mean M_j, std sqrt(M_j)
+    off = np.array([0, 1000, 5000])
+    eps = P.l2_bounds(2.0, off)
+    assert eps ** 2 == pytest.approx(4.0 * np.array([1000 + 2 * math.sqrt(1000), 4000 + 2 * math.sqrt(4000)]))
+    draws = np.array([np.sum(np.abs(synth.noise_unit(4000, s)) ** 2) for s in range(200)])
+    assert abs(draws.mean() - 4000) < 4 * math.sqrt(4000) / math.sqrt(200) * 3
+    assert abs(draws.std() - math.sqrt(4000)) < 0.25 * math.sqrt(4000)
+
+
+def test_input_snr_definition():
+    x, wu, wv, off = synth.small_case(16, 2000, seed=21)
+    noise = synth.noise_unit(2000, 5)
+    pb = P.make_problem(x, wu, wv, off, noise, 20.0, np.ones((16, 16)), with_eta=False)
+    y0 = pb.op.phi(x)
+    assert pb.sigma ** 2 == pytest.approx(np.mean(np.abs(y0) ** 2) / 100.0, rel=1e-12)
+    assert pb.y.dtype == np.complex128
+    assert np.array_equal(pb.y, pb.y.astype(np.complex64).astype(np.complex128))
