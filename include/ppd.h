@@ -1,0 +1,223 @@
+/*
+ * ppd.h -- C ABI of libppd, a gfx950 (MI355X) implementation of the
+ * per-iteration hot path of the preconditioned primal-dual (PPD) imager of
+ * Onose, Dabbech & Wiaux (2017), "An accelerated splitting algorithm for
+ * radio-interferometric imaging: when natural and uniform weighting meet".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers are DEVICE pointers unless the comment says HOST.  The caller
+ * owns every buffer it passes; the library owns only the plan and the
+ * device memory the plan allocates at creation (freed by ppd_plan_destroy).
+ * All launches are asynchronous on the plan's stream (see
+ * ppd_plan_set_stream); entry points that return host values synchronise
+ * that stream and say so.  Arguments are validated on the host before any
+ * launch, so a non-zero status leaves every output untouched.  A plan is not
+ * thread safe: use one plan per stream.  No exception crosses the ABI.
+ *
+ * Layouts: an image is ny rows x nx columns, row-major, float32; row r is
+ * the v axis, column c the u axis, pixel (ny/2, nx/2) is the phase centre.
+ * Complex arrays are interleaved (re, im): complex64 = 2 x float32,
+ * complex128 = 2 x float64.  SARA coefficient / dual arrays are
+ * [9][ny][nx] float32, basis 0 = Dirac, basis p = Daubechies-p (p = 1..8),
+ * each basis in the Mallat pyramid layout of the image size.
+ *
+ * Visibility order: per-visibility arrays are indexed in PLAN order by
+ * default -- the visibilities of each data block stay inside that block's
+ * range [block_off[j], block_off[j+1]) but are re-ordered by grid tile.
+ * ppd_plan_permutation / ppd_plan_permute convert from and to USER order
+ * (the order of omega_u / omega_v at plan creation).
+ */
+#ifndef PPD_H
+#define PPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PPD_OK            0
+#define PPD_EINVAL       -1   /* bad argument; nothing was launched          */
+#define PPD_ENOMEM       -2   /* device allocation failed at plan creation   */
+#define PPD_EDEVICE      -3   /* a HIP runtime call failed                   */
+#define PPD_ENONFINITE   -4   /* iteration statistics became NaN or Inf      */
+#define PPD_EUNSUPPORTED -5   /* valid but not implemented (e.g. sizes)      */
+
+/* Human-readable text for a status code (static storage). */
+const char* ppd_strerror(int status);
+/* Text of the last error raised on this thread (static per thread). */
+const char* ppd_last_error(void);
+
+/* ---- plan -------------------------------------------------------------- */
+typedef struct ppd_plan ppd_plan;
+
+typedef struct {
+  int32_t nx, ny;             /* image size; powers of two, 16 <= n <= 2048,
+                                 divisible by 2^levels                          */
+  int64_t M;                  /* number of visibilities, 1 <= M < 2^31          */
+  int32_t d;                  /* number of data blocks y_j (Sec. 3.1), >= 1     */
+  const int64_t* block_off;   /* HOST [d+1], 0 = off[0] < off[1] < .. = M       */
+  const float* omega_u;       /* HOST [M] u frequencies, rad/pixel in [-pi, pi) */
+  const float* omega_v;       /* HOST [M] v frequencies, rad/pixel in [-pi, pi) */
+  const float* theta;         /* HOST [M] natural weights 1/sigma_e (Sec. 2), or
+                                 NULL for theta = 1                              */
+  double kb_beta;             /* Kaiser-Bessel shape; <= 0 selects the default
+                                 pi sqrt(35.2) (width 8, 2x oversampling)        */
+  int32_t levels;             /* SARA decomposition levels (1..6), 0 -> 3       */
+  int32_t tile;               /* gridding tile edge in grid cells: 16, 32 or 64;
+                                 0 -> 32                                         */
+  int32_t chunk;              /* max visibilities per work chunk, 0 -> 1024     */
+} ppd_plan_desc;
+
+/* Create a plan: validates desc, bins the visibilities by (block, tile) on
+ * the host, uploads the sorted coverage, Kaiser-Bessel polynomial
+ * coefficients, deapodisation factors, FFT twiddles and Daubechies filters,
+ * and allocates the plan's work buffers.  Synchronous.  `stream` is a
+ * hipStream_t (NULL = default stream) used by every later call. */
+int ppd_plan_create(ppd_plan** plan, const ppd_plan_desc* desc, void* stream);
+int ppd_plan_destroy(ppd_plan* plan);
+int ppd_plan_set_stream(ppd_plan* plan, void* stream);
+
+typedef struct {
+  int32_t nx, ny, Kx, Ky;     /* image and oversampled grid sizes (K = 2 n)     */
+  int64_t M;
+  int32_t d, levels, tile, chunk;
+  int32_t n_chunks;           /* work chunks (one workgroup each)               */
+  double kb_beta;
+  size_t device_bytes;        /* device memory owned by the plan                */
+} ppd_plan_info;
+int ppd_plan_get_info(const ppd_plan* plan, ppd_plan_info* info /* HOST */);
+
+/* perm[p] = user index of plan position p.  HOST [M] int64.  Synchronous. */
+int ppd_plan_permutation(const ppd_plan* plan, int64_t* perm /* HOST */);
+
+#define PPD_USER_TO_PLAN 0
+#define PPD_PLAN_TO_USER 1
+/* Re-order a per-visibility device array (elem_bytes in {4, 8, 16}). */
+int ppd_plan_permute(ppd_plan* plan, int direction, const void* in, void* out, int elem_bytes);
+
+/* ---- measurement operator (Sec. 2: Phi = Theta G F Z) ------------------ */
+#define PPD_ORDER_PLAN 0
+#define PPD_ORDER_USER 1
+
+/* y = Theta G F Z x (Sec. 2): Kaiser-Bessel 8x8 degridding of the 2x
+ * oversampled, deapodised FFT of the image.  x: [ny][nx] float32.
+ * y: [M] complex64 in the given order. */
+int ppd_phi(ppd_plan* plan, const float* x, float* y, int order);
+
+/* x = Re(Z^H F^H G^H Theta^H y), the adjoint of ppd_phi for a real image
+ * (Sec. 2; step 12 and the sum of step 28 of Algorithm 3).
+ * y: [M] complex64 in the given order.  x: [ny][nx] float32. */
+int ppd_phit(ppd_plan* plan, const float* y, float* x, int order);
+
+/* ---- SARA sparsity operator (Sec. 5.1: Dirac + Daubechies 1..8) -------- */
+#define PPD_SARA_ANALYSIS  0   /* out[9][ny][nx] = Psi^H in  (in: image)        */
+#define PPD_SARA_SYNTHESIS 1   /* out[ny][nx] = Psi in       (in: [9][ny][nx])  */
+#define PPD_SARA_DUAL      2   /* Algorithm 3 steps 19-21 with W = I:
+                                  u <- u + lambda (clip(u + Psi^H in, +-alpha) - u),
+                                  out[ny][nx] = Psi u  (in: image, u_inout used) */
+/* Psi = (1/3)[I, W_1, .., W_8] with W_p the orthonormal periodised 2D
+ * Daubechies-p DWT, so Psi Psi^H = I.  u_inout may be NULL unless op is
+ * PPD_SARA_DUAL.  (I - S_alpha) is the soft-threshold complement of
+ * Sec. 3.3, i.e. a clip to [-alpha, alpha]. */
+int ppd_sara(ppd_plan* plan, int op, const float* in, float* out, float* u_inout,
+             float alpha, float lambda);
+
+/* ---- data-fidelity dual: ellipsoid projection (Sec. 4.1, Algorithm 2) -- */
+/* n_itr forward-backward iterations, per block j,
+ *     z <- P_B(z - mu U (z - w)),   P_B the projection onto
+ *     {z : ||z - y_j||_2 <= eps_j},
+ * approximating prox^U_h(w) of eq. elip-proj-1.  FP64 arithmetic and
+ * block norms.  w, zbar_inout: [M] complex128; y: [M] complex64;
+ * U: [M] float64 > 0; eps: HOST [d] float64 > 0; mu > 0.  Plan order. */
+int ppd_ellipsoid_proj(ppd_plan* plan, const double* w, const float* y, const double* U,
+                       const double* eps, int n_itr, double mu, double* zbar_inout);
+
+/* ---- setup quantities (Sec. 4.3, Sec. 5.1) ------------------------------ */
+/* Uniform-weighting preconditioner: the inverse sampling density near each
+ * visibility.  Points are counted on an ny x nx u-v cell grid, cell
+ * floor((omega + pi) n / (2 pi)) clamped to n - 1; U_e = c_min / c_e so that
+ * max U = 1.  U: [M] float64, plan order. */
+int ppd_uniform_weights(ppd_plan* plan, double* U);
+
+/* ||U^1/2 Phi||_S^2 by power iteration on x -> Re Phi^H (U Phi x) from the
+ * start image x0 ([ny][nx] float32; not modified); U may be NULL (U = 1).
+ * Stops when the relative change of the estimate is <= tol or after
+ * max_iter iterations.  Synchronous; result in *norm2 (HOST). */
+int ppd_op_norm(ppd_plan* plan, const double* U, const float* x0, int max_iter, double tol,
+                double* norm2, int* iters);
+
+/* ---- Algorithm 3 (PPD) -------------------------------------------------- */
+typedef struct {
+  float* x;        /* [ny][nx] primal image x                                 */
+  float* xt;       /* [ny][nx] x tilde                                        */
+  float* v;        /* [M] complex64 data duals v_j (plan order)               */
+  float* u;        /* [9][ny][nx] sparsity duals u_i                          */
+  double* z;       /* [M] complex128 Algorithm 2 iterate (warm start)         */
+  int64_t iter;    /* iterations done; advanced by ppd_iterate                */
+} ppd_state;
+
+#define PPD_FORM_FUSED 0   /* one launch per step for all blocks, dual update
+                              fused into (de)gridding, FP64 projection        */
+#define PPD_FORM_PLAIN 1   /* unfused reference form: Phi, per-block FP64
+                              dual kernels, Phi^H, each a separate launch     */
+
+typedef struct {
+  double tau, eta, zeta, lambda;   /* Algorithm 3 step sizes and relaxation   */
+  double alpha;                    /* l1 dual clip kappa ||Psi W||_S^2        */
+  double mu;                       /* Algorithm 2 step, <= 1 / max U          */
+  int32_t n_itr;                   /* Algorithm 2 iterations (>= 1)           */
+  int32_t form;                    /* PPD_FORM_*                              */
+  int32_t use_graph;               /* replay one captured iteration as a HIP graph */
+  int32_t pad_;
+  const float* y;                  /* [M] complex64 data, plan order          */
+  const double* U;                 /* [M] float64 preconditioner, plan order  */
+  const double* eps;               /* HOST [d] l2 bounds                      */
+  const float* x_true;             /* optional [ny][nx] reference for SNR     */
+} ppd_params;
+
+typedef struct {
+  int64_t iter;          /* state->iter after the call                       */
+  double rel_change;     /* ||x_t - x_{t-1}|| / ||x_t|| of the last iteration */
+  double x_norm;         /* ||x_t||                                          */
+  double snr_db;         /* 20 log10(||x_true|| / ||x_true - x_t||), NaN if no x_true */
+  double residual_max;   /* max_j ||Theta_j G_j F Z x~_{t-1} - y_j|| / eps_j  */
+} ppd_stats;
+
+/* Run n_iter iterations of Algorithm 3 (no randomisation: every block and
+ * basis is updated each iteration) on `state`.  Step 10 is read as
+ * vbar_j = U_j (w_j - prox^U_h(w_j)), w_j = U_j^{-1} v_j + Theta_j G_j a,
+ * with the prox approximated by n_itr Algorithm 2 iterations warm-started
+ * from state->z.  W_i = I.  If stats (HOST) is non-NULL the call
+ * synchronises and fills it (and residual[d], HOST, if non-NULL) from FP64
+ * reductions of the last iteration. */
+int ppd_iterate(ppd_plan* plan, ppd_state* state, const ppd_params* params, int n_iter,
+                ppd_stats* stats, double* residual);
+
+/* ---- per-kernel timing (HIP events around each launch) ----------------- */
+/* When enabled, the plan records a pair of HIP events around every kernel
+ * it launches (not inside captured graphs).  ppd_timing_read synchronises
+ * and returns, for up to `cap` kernel kinds, the name, launch count and
+ * total milliseconds since the last reset. */
+int ppd_timing_enable(ppd_plan* plan, int on);
+int ppd_timing_reset(ppd_plan* plan);
+int ppd_timing_read(ppd_plan* plan, int cap, const char** names /* HOST */,
+                    int64_t* counts /* HOST */, double* total_ms /* HOST */, int* n_kinds);
+
+/* ---- host-side helpers (no device work; used by CPU tests) ------------- */
+/* The 8 per-axis Kaiser-Bessel interpolation weights the kernels use, for
+ * n fractional offsets s in [0, 1): w[i][m] ~ phi(s_i + 3 - m), m = 0..7,
+ * evaluated exactly as on the device (degree-9 polynomial per tap, float32
+ * Horner).  HOST pointers. */
+int ppd_kb_weights_host(double kb_beta, int64_t n, const float* s, float* w);
+/* Daubechies-p low-pass filter (p = 1..8, 2p taps) as the library computes
+ * it (float64, before rounding to float32).  HOST pointer. */
+int ppd_daubechies_host(int p, double* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPD_H */

@@ -1,0 +1,287 @@
+// Data-fidelity dual update (Algorithm 3 steps 10-11) and Algorithm 2,
+// FP64: the standalone ellipsoid projection entry point, the unfused
+// per-block ("plain") form of the dual update, and the uniform-weighting
+// preconditioner (inverse local sampling density, Sec. 4.3).
+#include <cmath>
+
+#include "ppd_internal.h"
+
+namespace ppd {
+namespace {
+
+__device__ inline double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+__device__ inline double block_norm2(int j, const double* __restrict__ part,
+                                     const int32_t* __restrict__ bids, const int32_t* __restrict__ boff) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int c = boff[j] + lane; c < boff[j + 1]; c += 64) s += part[bids[c]];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  return s;
+}
+
+// One Algorithm 2 iteration over every block, chunk by chunk.
+//   mode 0: partials of ||q - y||^2, q = z - mu U (z - w)   (z unchanged)
+//   mode 1: z <- P_B(q) with the norms in part_in, then partials of the next q
+//   mode 2: z <- P_B(q) only
+__global__ __launch_bounds__(256) void k_alg2(
+    int mode, const Chunk* __restrict__ chunks, int n_chunks, const double2* __restrict__ w,
+    const float2* __restrict__ y, const double* __restrict__ U, double2* __restrict__ z, double mu,
+    const double* __restrict__ part_in, double* __restrict__ part_out,
+    const int32_t* __restrict__ bids, const int32_t* __restrict__ boff, const double* __restrict__ eps) {
+  __shared__ double s_fac;
+  __shared__ int s_inside;
+  __shared__ double red[16];
+  const int ci = xcd_remap(blockIdx.x, gridDim.x);
+  if (ci >= n_chunks) return;
+  const Chunk ch = chunks[ci];
+  if (mode != 0 && threadIdx.x < 64) {
+    const double r = sqrt(block_norm2(ch.block, part_in, bids, boff));
+    if (threadIdx.x == 0) {
+      const double e = eps[ch.block];
+      s_inside = r <= e;
+      s_fac = r > e ? e / r : 1.0;
+    }
+  }
+  __syncthreads();
+  double qn = 0.0;
+  for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
+    const int pi = ch.start + k;
+    const double2 we = w[pi];
+    double2 ze = z[pi];
+    const double mU = mu * U[pi];
+    const float2 ye = y[pi];
+    if (mode != 0) {
+      const double qx = ze.x - mU * (ze.x - we.x), qy = ze.y - mU * (ze.y - we.y);
+      if (!s_inside) {
+        ze.x = double(ye.x) + (qx - double(ye.x)) * s_fac;
+        ze.y = double(ye.y) + (qy - double(ye.y)) * s_fac;
+      } else {
+        ze.x = qx;
+        ze.y = qy;
+      }
+      z[pi] = ze;
+    }
+    if (mode != 2) {
+      const double dx = (ze.x - mU * (ze.x - we.x)) - double(ye.x);
+      const double dy = (ze.y - mU * (ze.y - we.y)) - double(ye.y);
+      qn += dx * dx + dy * dy;
+    }
+  }
+  if (mode != 2) {
+    qn = block_sum(qn, red);
+    if (threadIdx.x == 0) part_out[ci] = qn;
+  }
+}
+
+// ---- plain form: one block at a time, each step its own launch ---------
+constexpr int PL_THREADS = 256;
+constexpr int PL_MAX_BLOCKS = 512;
+
+// w = U^-1 v + yhat, and partials of ||yhat - y||^2 (residual statistics)
+__global__ void k_pl_w(int64_t b0, int64_t b1, const float2* __restrict__ v, const double* __restrict__ U,
+                       const float2* __restrict__ yhat, const float2* __restrict__ y,
+                       double2* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[16];
+  double rn = 0.0;
+  for (int64_t i = b0 + blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < b1; i += int64_t(gridDim.x) * blockDim.x) {
+    const float2 ve = v[i], g = yhat[i], ye = y[i];
+    const double Ue = U[i];
+    w[i] = make_double2(double(ve.x) / Ue + double(g.x), double(ve.y) / Ue + double(g.y));
+    const double ex = double(g.x) - double(ye.x), ey = double(g.y) - double(ye.y);
+    rn += ex * ex + ey * ey;
+  }
+  rn = block_sum(rn, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = rn;
+}
+
+// q = z - mu U (z - w) and partials of ||q - y||^2
+__global__ void k_pl_q(int64_t b0, int64_t b1, const double2* __restrict__ w, const double2* __restrict__ z,
+                       const double* __restrict__ U, const float2* __restrict__ y, double mu,
+                       double2* __restrict__ q, double* __restrict__ part) {
+  __shared__ double red[16];
+  double qn = 0.0;
+  for (int64_t i = b0 + blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < b1; i += int64_t(gridDim.x) * blockDim.x) {
+    const double2 we = w[i], ze = z[i];
+    const double mU = mu * U[i];
+    const double qx = ze.x - mU * (ze.x - we.x), qy = ze.y - mU * (ze.y - we.y);
+    q[i] = make_double2(qx, qy);
+    const float2 ye = y[i];
+    const double dx = qx - double(ye.x), dy = qy - double(ye.y);
+    qn += dx * dx + dy * dy;
+  }
+  qn = block_sum(qn, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = qn;
+}
+
+// out[slot] = sum of n partials (one wave, fixed order)
+__global__ void k_pl_reduce(const double* __restrict__ part, int n, double* __restrict__ out, int slot) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) s += part[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (threadIdx.x == 0) out[slot] = s;
+}
+
+// z = P_B(q) (Sec. 3.3, eq. proj-L2) with ||q - y||^2 in *norm2
+__global__ void k_pl_proj(int64_t b0, int64_t b1, const double2* __restrict__ q, const float2* __restrict__ y,
+                          const double* __restrict__ norm2, const double* __restrict__ eps, int j,
+                          double2* __restrict__ z) {
+  const double r = sqrt(*norm2), e = eps[j];
+  const bool inside = r <= e;
+  const double f = inside ? 1.0 : e / r;
+  for (int64_t i = b0 + blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < b1; i += int64_t(gridDim.x) * blockDim.x) {
+    const double2 qe = q[i];
+    if (inside) {
+      z[i] = qe;
+    } else {
+      const float2 ye = y[i];
+      z[i] = make_double2(double(ye.x) + (qe.x - double(ye.x)) * f, double(ye.y) + (qe.y - double(ye.y)) * f);
+    }
+  }
+}
+
+// vbar = U (w - z); v <- v + lambda (vbar - v)
+__global__ void k_pl_finish(int64_t b0, int64_t b1, const double2* __restrict__ w, const double2* __restrict__ z,
+                            const double* __restrict__ U, double lambda, float2* __restrict__ v) {
+  for (int64_t i = b0 + blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < b1; i += int64_t(gridDim.x) * blockDim.x) {
+    const double2 we = w[i], ze = z[i];
+    const double Ue = U[i];
+    const float2 vo = v[i];
+    const double vbx = Ue * (we.x - ze.x), vby = Ue * (we.y - ze.y);
+    v[i] = make_float2(float(double(vo.x) + lambda * (vbx - double(vo.x))),
+                       float(double(vo.y) + lambda * (vby - double(vo.y))));
+  }
+}
+
+// ---- uniform-weighting preconditioner ----------------------------------
+__device__ __forceinline__ int density_cell(float w, int n) {
+  // floor((w + pi) n / (2 pi)), evaluated exactly in this order, clamped
+  const double a = __dadd_rn(double(w), M_PI);
+  const double b = __dmul_rn(a, double(n));
+  const double c = __ddiv_rn(b, 2.0 * M_PI);
+  int i = int(floor(c));
+  return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+}
+
+__global__ void k_hist(const float* __restrict__ wu, const float* __restrict__ wv, int64_t M, int nx, int ny,
+                       int32_t* __restrict__ counts) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < M; i += int64_t(gridDim.x) * blockDim.x) {
+    const int cu = density_cell(wu[i], nx), cv = density_cell(wv[i], ny);
+    atomicAdd(&counts[cv * nx + cu], 1);
+  }
+}
+
+__global__ void k_hist_min(const float* __restrict__ wu, const float* __restrict__ wv, int64_t M, int nx, int ny,
+                           const int32_t* __restrict__ counts, int32_t* __restrict__ cmin) {
+  int m = 0x7fffffff;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < M; i += int64_t(gridDim.x) * blockDim.x) {
+    const int cu = density_cell(wu[i], nx), cv = density_cell(wv[i], ny);
+    m = min(m, counts[cv * nx + cu]);
+  }
+  for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMin(cmin, m);
+}
+
+__global__ void k_hist_u(const float* __restrict__ wu, const float* __restrict__ wv, int64_t M, int nx, int ny,
+                         const int32_t* __restrict__ counts, const int32_t* __restrict__ cmin,
+                         double* __restrict__ U) {
+  const double c0 = double(*cmin);
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < M; i += int64_t(gridDim.x) * blockDim.x) {
+    const int cu = density_cell(wu[i], nx), cv = density_cell(wv[i], ny);
+    U[i] = c0 / double(counts[cv * nx + cu]);
+  }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) a[i] = v;
+}
+
+int grid_blocks(int64_t n) { return int(std::min<int64_t>((n + PL_THREADS - 1) / PL_THREADS, PL_MAX_BLOCKS)); }
+
+}  // namespace
+
+int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* y, const double* U, double2* z,
+                double mu, const double* part_in, double* part_out) {
+  int slot;
+  PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
+  hipLaunchKernelGGL(k_alg2, dim3(p->n_launch), dim3(256), 0, p->stream, mode, p->chunks, p->n_chunks,
+                     w, y, U, z, mu, part_in, part_out, p->bchunk_ids, p->bchunk_off_d, p->eps_d);
+  PPD_HIP(hipGetLastError());
+  return timer_end(p, slot);
+}
+
+// Unfused reference form of steps 10-11: per block, per sub-iteration,
+// separate FP64 launches.  Expects Theta G F Z x~ in p->ybuf (plan order).
+int plain_dual(ppd_plan* p, const DualArgs& a) {
+  for (int j = 0; j < p->d; ++j) {
+    const int64_t b0 = p->block_off[j], b1 = p->block_off[j + 1];
+    const int G = grid_blocks(b1 - b0);
+    int slot;
+    PPD_TRY(timer_begin(p, KK_PLAIN_DUAL, &slot));
+    hipLaunchKernelGGL(k_pl_w, dim3(G), dim3(PL_THREADS), 0, p->stream, b0, b1, a.v, a.U, p->ybuf, a.y,
+                       p->wbuf, p->pl_part);
+    hipLaunchKernelGGL(k_pl_reduce, dim3(1), dim3(64), 0, p->stream, p->pl_part, G, p->res_sq, j);
+    for (int s = 0; s < a.n_itr; ++s) {
+      hipLaunchKernelGGL(k_pl_q, dim3(G), dim3(PL_THREADS), 0, p->stream, b0, b1, p->wbuf, a.z, a.U, a.y,
+                         a.mu, p->qbuf, p->pl_part);
+      hipLaunchKernelGGL(k_pl_reduce, dim3(1), dim3(64), 0, p->stream, p->pl_part, G, p->pl_scalar, 0);
+      hipLaunchKernelGGL(k_pl_proj, dim3(G), dim3(PL_THREADS), 0, p->stream, b0, b1, p->qbuf, a.y,
+                         p->pl_scalar, p->eps_d, j, a.z);
+    }
+    hipLaunchKernelGGL(k_pl_finish, dim3(G), dim3(PL_THREADS), 0, p->stream, b0, b1, p->wbuf, a.z, a.U,
+                       a.lambda, a.v);
+    PPD_HIP(hipGetLastError());
+    PPD_TRY(timer_end(p, slot));
+  }
+  return PPD_OK;
+}
+
+}  // namespace ppd
+
+using namespace ppd;
+
+extern "C" int ppd_ellipsoid_proj(ppd_plan* p, const double* w, const float* y, const double* U,
+                                  const double* eps, int n_itr, double mu, double* zbar) {
+  if (!p || !w || !y || !U || !eps || !zbar) return fail(PPD_EINVAL, "ppd_ellipsoid_proj: NULL argument");
+  if (n_itr < 1) return fail(PPD_EINVAL, "ppd_ellipsoid_proj: n_itr must be >= 1");
+  if (!(mu > 0.0) || !std::isfinite(mu)) return fail(PPD_EINVAL, "ppd_ellipsoid_proj: mu must be > 0");
+  PPD_TRY(upload_eps(p, eps));
+  const double2* w2 = reinterpret_cast<const double2*>(w);
+  const float2* y2 = reinterpret_cast<const float2*>(y);
+  double2* z2 = reinterpret_cast<double2*>(zbar);
+  double* pa = p->part;
+  double* pb = p->part + p->n_chunks;
+  PPD_TRY(alg2_launch(p, 0, w2, y2, U, z2, mu, nullptr, pa));
+  for (int s = 1; s < n_itr; ++s) {
+    PPD_TRY(alg2_launch(p, 1, w2, y2, U, z2, mu, pa, pb));
+    std::swap(pa, pb);
+  }
+  return alg2_launch(p, 2, w2, y2, U, z2, mu, pa, nullptr);
+}
+
+extern "C" int ppd_uniform_weights(ppd_plan* p, double* U) {
+  if (!p || !U) return fail(PPD_EINVAL, "ppd_uniform_weights: NULL argument");
+  int slot;
+  PPD_TRY(timer_begin(p, KK_HIST, &slot));
+  const int64_t N = int64_t(p->nx) * p->ny;
+  const int gb = int(std::min<int64_t>((p->M + 255) / 256, 2048));
+  hipLaunchKernelGGL(k_fill_i32, dim3(int(std::min<int64_t>((N + 255) / 256, 2048))), dim3(256), 0,
+                     p->stream, p->icount, N, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, p->stream, p->imin, int64_t(1), 0x7fffffff);
+  hipLaunchKernelGGL(k_hist, dim3(gb), dim3(256), 0, p->stream, p->wu, p->wv, p->M, p->nx, p->ny, p->icount);
+  hipLaunchKernelGGL(k_hist_min, dim3(gb), dim3(256), 0, p->stream, p->wu, p->wv, p->M, p->nx, p->ny,
+                     p->icount, p->imin);
+  hipLaunchKernelGGL(k_hist_u, dim3(gb), dim3(256), 0, p->stream, p->wu, p->wv, p->M, p->nx, p->ny,
+                     p->icount, p->imin, U);
+  PPD_HIP(hipGetLastError());
+  return timer_end(p, slot);
+}

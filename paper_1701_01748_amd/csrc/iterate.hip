@@ -1,0 +1,300 @@
+// Algorithm 3 driver (PPD; PD when U = 1), FP64 statistics, the operator
+// norm of U^1/2 Phi by power iteration, and HIP-graph replay of one
+// iteration.
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "ppd_internal.h"
+
+namespace ppd {
+
+int primal_partial_count(ppd_plan* p);
+int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* y, const double* U, double2* z,
+                double mu, const double* part_in, double* part_out);
+
+namespace {
+
+// One workgroup of 64 threads: statistics of the last iteration.
+// out: [0] rel change, [1] ||x||, [2] SNR dB, [3] max_j r_j / eps_j,
+//      [4..7] raw sums, [8 + j] r_j = ||Theta_j G_j F Z x~ - y_j||.
+__global__ void k_stats(const double* __restrict__ ppart, int nparts, const double* __restrict__ rpart,
+                        const int32_t* __restrict__ bids, const int32_t* __restrict__ boff,
+                        const double* __restrict__ res_sq, int use_res_sq, const double* __restrict__ eps,
+                        int d, int has_truth, double* __restrict__ out) {
+  const int lane = threadIdx.x;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = lane; i < nparts; i += 64)
+    for (int k = 0; k < 4; ++k) s[k] += ppart[4 * i + k];
+  for (int k = 0; k < 4; ++k)
+    for (int o = 32; o > 0; o >>= 1) s[k] += __shfl_xor(s[k], o);
+  double rmax = 0.0;
+  for (int j = 0; j < d; ++j) {
+    double r2;
+    if (use_res_sq) {
+      r2 = res_sq[j];
+    } else {
+      r2 = 0.0;
+      for (int c = boff[j] + lane; c < boff[j + 1]; c += 64) r2 += rpart[bids[c]];
+      for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o);
+    }
+    const double r = sqrt(r2);
+    rmax = fmax(rmax, r / eps[j]);
+    if (lane == 0) out[8 + j] = r;
+  }
+  if (lane == 0) {
+    out[0] = sqrt(s[0] / s[1]);
+    out[1] = sqrt(s[1]);
+    out[2] = has_truth ? 20.0 * log10(sqrt(s[3] / s[2])) : __builtin_nan("");
+    out[3] = rmax;
+    out[4] = s[0];
+    out[5] = s[1];
+    out[6] = s[2];
+    out[7] = s[3];
+  }
+}
+
+__global__ void k_img_norm2(const float* __restrict__ a, int64_t n, double* __restrict__ part) {
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const double v = a[i];
+    s += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  __shared__ double red[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int n, double* __restrict__ out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) s += part[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ void k_img_scale(const float* __restrict__ a, int64_t n, double s, float* __restrict__ b) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = float(double(a[i]) * s);
+}
+
+__global__ void k_vis_mul_U(float2* __restrict__ y, const double* __restrict__ U, int64_t M) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < M; i += int64_t(gridDim.x) * blockDim.x) {
+    const float2 v = y[i];
+    const double u = U[i];
+    y[i] = make_float2(float(double(v.x) * u), float(double(v.y) * u));
+  }
+}
+
+int img_norm(ppd_plan* p, const float* a, double* out_host) {
+  const int64_t n = int64_t(p->nx) * p->ny;
+  const int G = int(std::min<int64_t>((n + 255) / 256, 512));
+  hipLaunchKernelGGL(k_img_norm2, dim3(G), dim3(256), 0, p->stream, a, n, p->pl_part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, p->stream, p->pl_part, G, p->pl_scalar);
+  PPD_HIP(hipGetLastError());
+  double v = 0.0;
+  PPD_HIP(hipMemcpyAsync(&v, p->pl_scalar, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  PPD_HIP(hipStreamSynchronize(p->stream));
+  *out_host = std::sqrt(v);
+  return PPD_OK;
+}
+
+int img_scale(ppd_plan* p, const float* a, double s, float* b) {
+  const int64_t n = int64_t(p->nx) * p->ny;
+  hipLaunchKernelGGL(k_img_scale, dim3(int(std::min<int64_t>((n + 255) / 256, 2048))), dim3(256), 0,
+                     p->stream, a, n, s, b);
+  PPD_HIP(hipGetLastError());
+  return PPD_OK;
+}
+
+struct IterCtx {
+  DualArgs dual;
+  PrimalArgs primal;
+  float* u;
+  float alpha, lambda;
+  int form;
+};
+
+// One iteration of Algorithm 3 (no randomisation) on the plan's stream.
+int one_iteration(ppd_plan* p, const IterCtx& c) {
+  const float* xt = c.primal.xt;
+  PPD_TRY(fft_forward(p, xt));                              // step 4: a = F Z x~
+  if (c.form == PPD_FORM_FUSED) {
+    PPD_TRY(zero_grid(p, p->grid_a));
+    double* pa = p->part;
+    double* pb = p->part + p->n_chunks;
+    PPD_TRY(degrid_dual(p, c.dual, pa));                    // step 10 argument, first Alg. 2 step
+    for (int s = 1; s < c.dual.n_itr; ++s) {
+      PPD_TRY(alg2_launch(p, 1, p->wbuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb));
+      std::swap(pa, pb);
+    }
+    PPD_TRY(grid_dual(p, c.dual, pa));                      // steps 10-12
+  } else {
+    PPD_TRY(degrid_plain(p, p->ybuf));
+    PPD_TRY(plain_dual(p, c.dual));                         // steps 10-11, block by block
+    PPD_TRY(zero_grid(p, p->grid_a));
+    PPD_TRY(grid_plain(p, c.dual.v));                       // step 12
+  }
+  PPD_TRY(fft_cols_inverse(p));
+  PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda));        // steps 19-20
+  PPD_TRY(sara_synthesis(p, c.u, p->ut));                   // step 21, summed over i
+  return fft_rows_inverse_primal(p, c.primal);              // steps 28-30
+}
+
+std::string graph_key(const IterCtx& c) {
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d",
+                (void*)c.dual.y, (void*)c.dual.U, (void*)c.dual.v, (void*)c.dual.z, (void*)c.primal.x,
+                (void*)c.primal.xt, (void*)c.primal.x_true, (void*)c.u, (void*)c.primal.ut, c.dual.mu,
+                c.dual.lambda, c.primal.tau, c.primal.eta, c.primal.zeta, double(c.alpha),
+                double(c.lambda), c.dual.n_itr, c.form);
+  return std::string(buf);
+}
+
+}  // namespace
+
+int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq) {
+  int slot;
+  PPD_TRY(timer_begin(p, KK_STATS, &slot));
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, p->stream, p->ppart, primal_partial_count(p), p->rpart,
+                     p->bchunk_ids, p->bchunk_off_d, p->res_sq, use_res_sq, p->eps_d, p->d, has_truth,
+                     p->stats_d);
+  PPD_HIP(hipGetLastError());
+  return timer_end(p, slot);
+}
+
+}  // namespace ppd
+
+using namespace ppd;
+
+extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, int n_iter, ppd_stats* stats,
+                           double* residual) {
+  if (!p || !st || !prm) return fail(PPD_EINVAL, "ppd_iterate: NULL argument");
+  if (!st->x || !st->xt || !st->v || !st->u || !st->z || !prm->y || !prm->U || !prm->eps)
+    return fail(PPD_EINVAL, "ppd_iterate: state and params need x, xt, v, u, z, y, U, eps");
+  if (n_iter < 0) return fail(PPD_EINVAL, "ppd_iterate: n_iter must be >= 0");
+  if (prm->n_itr < 1) return fail(PPD_EINVAL, "ppd_iterate: n_itr must be >= 1");
+  if (prm->form != PPD_FORM_FUSED && prm->form != PPD_FORM_PLAIN)
+    return fail(PPD_EINVAL, "ppd_iterate: unknown form");
+  const double vals[6] = {prm->tau, prm->eta, prm->zeta, prm->lambda, prm->alpha, prm->mu};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(PPD_EINVAL, "ppd_iterate: non-finite parameter");
+  if (!(prm->tau > 0 && prm->eta > 0 && prm->zeta >= 0 && prm->lambda > 0 && prm->lambda <= 1 &&
+        prm->alpha >= 0 && prm->mu > 0))
+    return fail(PPD_EINVAL, "ppd_iterate: need tau, eta, mu > 0, zeta, alpha >= 0, 0 < lambda <= 1");
+  if (prm->use_graph && p->stream == nullptr)
+    return fail(PPD_EINVAL, "ppd_iterate: graph replay needs a non-default stream");
+  PPD_TRY(upload_eps(p, prm->eps));
+
+  IterCtx c{};
+  c.dual.y = reinterpret_cast<const float2*>(prm->y);
+  c.dual.U = prm->U;
+  c.dual.v = reinterpret_cast<float2*>(st->v);
+  c.dual.z = reinterpret_cast<double2*>(st->z);
+  c.dual.mu = prm->mu;
+  c.dual.lambda = prm->lambda;
+  c.dual.n_itr = prm->n_itr;
+  c.primal.x = st->x;
+  c.primal.xt = st->xt;
+  c.primal.ut = p->ut;
+  c.primal.x_true = prm->x_true;
+  c.primal.tau = prm->tau;
+  c.primal.eta = prm->eta;
+  c.primal.zeta = prm->zeta;
+  c.primal.lambda = prm->lambda;
+  c.primal.part = p->ppart;
+  c.u = st->u;
+  c.alpha = float(prm->alpha);
+  c.lambda = float(prm->lambda);
+  c.form = prm->form;
+
+  if (n_iter > 0) {
+    if (prm->use_graph) {
+      const std::string key = graph_key(c);
+      if (!p->graph_exec || key != p->graph_key) {
+        if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->graph_exec = nullptr;
+        p->graph = nullptr;
+        p->graph_key.clear();
+        PPD_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+        const int cst = one_iteration(p, c);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->stream, &g);
+        if (cst != PPD_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return cst;
+        }
+        if (e != hipSuccess) return fail(PPD_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        p->graph = g;
+        PPD_HIP(hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0));
+        p->graph_key = key;
+      }
+      for (int t = 0; t < n_iter; ++t) PPD_HIP(hipGraphLaunch(p->graph_exec, p->stream));
+    } else {
+      for (int t = 0; t < n_iter; ++t) PPD_TRY(one_iteration(p, c));
+    }
+    st->iter += n_iter;
+  }
+  if (stats || residual) {
+    if (n_iter == 0) return fail(PPD_EINVAL, "ppd_iterate: statistics need n_iter >= 1");
+    PPD_TRY(stats_finalize(p, prm->x_true != nullptr, prm->form == PPD_FORM_PLAIN));
+    std::vector<double> h(8 + p->d);
+    PPD_HIP(hipMemcpyAsync(h.data(), p->stats_d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, p->stream));
+    PPD_HIP(hipStreamSynchronize(p->stream));
+    if (stats) {
+      stats->iter = st->iter;
+      stats->rel_change = h[0];
+      stats->x_norm = h[1];
+      stats->snr_db = h[2];
+      stats->residual_max = h[3];
+    }
+    if (residual)
+      for (int j = 0; j < p->d; ++j) residual[j] = h[8 + j];
+    if (!std::isfinite(h[1]) || !std::isfinite(h[3]) || (prm->x_true && std::isnan(h[2])))
+      return fail(PPD_ENONFINITE, "ppd_iterate: non-finite statistics");
+  }
+  return PPD_OK;
+}
+
+extern "C" int ppd_op_norm(ppd_plan* p, const double* U, const float* x0, int max_iter, double tol,
+                           double* norm2, int* iters) {
+  if (!p || !x0 || !norm2) return fail(PPD_EINVAL, "ppd_op_norm: NULL argument");
+  if (max_iter < 1 || !(tol >= 0.0)) return fail(PPD_EINVAL, "ppd_op_norm: bad max_iter / tol");
+  double n0 = 0.0;
+  PPD_TRY(img_norm(p, x0, &n0));
+  if (!(n0 > 0.0) || !std::isfinite(n0)) return fail(PPD_EINVAL, "ppd_op_norm: start image must be non-zero");
+  PPD_TRY(img_scale(p, x0, 1.0 / n0, p->vec_tmp));
+  double lam = 0.0, lam_prev = 0.0;
+  int k = 0;
+  for (; k < max_iter; ++k) {
+    PPD_TRY(fft_forward(p, p->vec_tmp));
+    PPD_TRY(degrid_plain(p, p->ybuf));
+    if (U) {
+      hipLaunchKernelGGL(k_vis_mul_U, dim3(int(std::min<int64_t>((p->M + 255) / 256, 4096))), dim3(256), 0,
+                         p->stream, p->ybuf, U, p->M);
+      PPD_HIP(hipGetLastError());
+    }
+    PPD_TRY(zero_grid(p, p->grid_a));
+    PPD_TRY(grid_plain(p, p->ybuf));
+    PPD_TRY(fft_adjoint(p, p->img_tmp));
+    PPD_TRY(img_norm(p, p->img_tmp, &lam));
+    if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PPD_ENONFINITE, "ppd_op_norm: degenerate iterate");
+    PPD_TRY(img_scale(p, p->img_tmp, 1.0 / lam, p->vec_tmp));
+    if (k > 0 && std::fabs(lam - lam_prev) <= tol * lam) {
+      ++k;
+      break;
+    }
+    lam_prev = lam;
+  }
+  PPD_HIP(hipStreamSynchronize(p->stream));
+  *norm2 = lam;
+  if (iters) *iters = k;
+  return PPD_OK;
+}

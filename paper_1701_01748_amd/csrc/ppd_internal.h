@@ -1,0 +1,198 @@
+// Internal declarations of libppd (gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ppd.h"
+
+namespace ppd {
+
+// ---- errors -------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int status, const std::string& msg);
+
+#define PPD_HIP(expr)                                                           \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      return ::ppd::fail(PPD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define PPD_TRY(expr)                 \
+  do {                                \
+    int s_ = (expr);                  \
+    if (s_ != PPD_OK) return s_;      \
+  } while (0)
+
+// ---- constants ----------------------------------------------------------
+constexpr int KB_TAPS = 8;        // kernel width per axis
+constexpr int KB_DEG = 9;         // polynomial degree per tap
+constexpr int KB_NC = KB_DEG + 1; // coefficients per tap
+constexpr int N_BASES = 9;        // Dirac + db1..db8
+constexpr int FILT_STRIDE = 16;   // max Daubechies taps (db8)
+constexpr int MAX_XCD = 8;
+
+// One workgroup's work: visibilities [start, start+count) of plan order,
+// all in data block `block` with first tap in grid tile (tx, ty).
+struct Chunk {
+  int32_t start, count, tx, ty, block, pad0, pad1, pad2;
+};
+
+// Kernel kinds for the optional per-launch event timer.
+enum KernelKind {
+  KK_FFT_ROWS_FWD, KK_FFT_COLS_FWD, KK_DEGRID, KK_GRID, KK_FFT_COLS_INV, KK_FFT_ROWS_INV,
+  KK_ZERO, KK_PERMUTE, KK_SUBITER, KK_DWT, KK_IDWT, KK_STATS, KK_PLAIN_DUAL, KK_HIST,
+  KK_NORM, KK_MISC, KK_COUNT
+};
+const char* kernel_kind_name(int k);
+
+}  // namespace ppd
+
+struct ppd_plan {
+  // geometry
+  int nx = 0, ny = 0, Kx = 0, Ky = 0, log2Kx = 0, log2Ky = 0;
+  int64_t M = 0;
+  int d = 0, levels = 3, T = 32, chunk_max = 1024;
+  int tiles_x = 0, tiles_y = 0;
+  double beta = 0.0;
+  double su_scale = 0.0, sv_scale = 0.0;   // K / (2 pi) per axis
+  bool has_theta = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // host copies
+  std::vector<int64_t> block_off;          // [d+1]
+  std::vector<int32_t> perm_host;          // plan -> user
+  std::vector<ppd::Chunk> chunks_host;     // launch order
+  std::vector<int32_t> bchunk_off;         // [d+1] into bchunk_ids
+  int n_chunks = 0;
+  int n_launch = 0;                        // chunk launches padded to XCD multiple
+
+  // device: coverage and plan tables
+  float* wu = nullptr;
+  float* wv = nullptr;
+  float* theta = nullptr;
+  int32_t* perm = nullptr;
+  ppd::Chunk* chunks = nullptr;
+  int32_t* bchunk_ids = nullptr;           // chunk ids grouped by block
+  int32_t* bchunk_off_d = nullptr;         // [d+1]
+  int32_t* vis_block = nullptr;            // plan index -> block (plain form)
+  float* kbc = nullptr;                    // [8][10] tap polynomials
+  float* dpx = nullptr;                    // [nx] 1/phi_hat(n_c / Kx)
+  float* dpy = nullptr;                    // [ny] 1/phi_hat(n_r / Ky)
+  float2* twx = nullptr;                   // [Kx/2] exp(-2 pi i k / Kx)
+  float2* twy = nullptr;                   // [Ky/2]
+  float* filt = nullptr;                   // [8][2][16] lo / hi Daubechies filters
+
+  // device: work buffers
+  float2* grid_f = nullptr;                // forward spectrum  Ky x Kx
+  float2* grid_a = nullptr;                // adjoint accumulation Ky x Kx
+  float2* half = nullptr;                  // ny x Kx intermediate
+  float2* ybuf = nullptr;                  // [M] complex64 scratch
+  double2* wbuf = nullptr;                 // [M] complex128 w (dual prologue)
+  double2* qbuf = nullptr;                 // [M] complex128 (plain form)
+  double* part = nullptr;                  // [2][n_chunks] block-norm partials
+  double* rpart = nullptr;                 // [n_chunks] residual partials
+  double* eps_d = nullptr;                 // [d]
+  std::vector<double> eps_cache;
+  double* ppart = nullptr;                 // [ny][4] primal statistics partials
+  double* stats_d = nullptr;               // [8 + d]
+  float* sara_ll = nullptr;                // LL temporaries, analysis
+  float* sara_rec = nullptr;               // reconstruction temporaries
+  float* ut = nullptr;                     // [ny][nx] Psi u
+  float* img_tmp = nullptr;                // [ny][nx]
+  float* vec_tmp = nullptr;                // [ny][nx] power iteration
+  double* pl_part = nullptr;               // [1024] plain-form / image partials
+  double* res_sq = nullptr;                // [d] plain-form residual norms^2
+  double* pl_scalar = nullptr;             // [4]
+  int32_t* icount = nullptr;               // [ny][nx] sampling-density counts
+  int32_t* imin = nullptr;                 // [1]
+  size_t sara_ll_floats = 0;
+  size_t device_bytes = 0;
+  std::vector<void*> allocations;
+
+  // graph replay of one iteration
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::string graph_key;
+
+  // optional per-launch timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_pending;   // (kind, event pair index)
+  int64_t t_counts[ppd::KK_COUNT] = {};
+  double t_ms[ppd::KK_COUNT] = {};
+};
+
+namespace ppd {
+
+// launch bracketing for the per-kernel timer
+int timer_begin(ppd_plan* p, int kind, int* slot);
+int timer_end(ppd_plan* p, int slot);
+
+// ---- component launchers (each returns a PPD_* status) -------------------
+int fft_forward(ppd_plan* p, const float* x);                  // x -> grid_f
+int fft_adjoint(ppd_plan* p, float* x);                        // grid_a -> x (plain)
+int fft_cols_inverse(ppd_plan* p);                             // grid_a -> half
+struct PrimalArgs {
+  float* x; float* xt; const float* ut; const float* x_true;
+  double tau, eta, zeta, lambda;
+  double* part;                                                // [ny][4]
+};
+int fft_rows_inverse_primal(ppd_plan* p, const PrimalArgs& a);  // half -> primal update
+int zero_grid(ppd_plan* p, float2* g);
+
+int degrid_plain(ppd_plan* p, float2* out);                    // grid_f -> out (plan order)
+struct DualArgs {
+  const float2* y; const double* U; float2* v; double2* z;
+  double mu, lambda;
+  int n_itr;
+};
+int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out);   // grid_f -> wbuf
+int grid_plain(ppd_plan* p, const float2* v);                 // v -> grid_a (accumulate)
+int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in);  // dual finish + grid
+
+int plain_dual(ppd_plan* p, const DualArgs& a);               // per-block unfused dual update
+int permute(ppd_plan* p, int direction, const void* in, void* out, int elem_bytes);
+
+int sara_analysis(ppd_plan* p, const float* x, float* coef);
+int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda);
+int sara_synthesis(ppd_plan* p, const float* u, float* out);
+
+int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq);
+int upload_eps(ppd_plan* p, const double* eps_host);
+
+// host-side setup helpers
+void kb_tap_polynomials(double beta, float* coef /* [8][KB_NC] */);
+double kb_ft(double xi, double beta);
+void daubechies(int p, double* h);
+
+}  // namespace ppd
+
+// ---- device helpers --------------------------------------------------------
+namespace ppd {
+
+__host__ __device__ inline void kb_weights(float s, const float* __restrict__ c, float* w) {
+  const float x = 2.0f * s - 1.0f;
+#pragma unroll
+  for (int m = 0; m < KB_TAPS; ++m) {
+    float acc = c[m * KB_NC + KB_DEG];
+#pragma unroll
+    for (int k = KB_DEG - 1; k >= 0; --k) acc = fmaf(acc, x, c[m * KB_NC + k]);
+    w[m] = acc;
+  }
+}
+
+// XCD-aware remap: consecutive workgroup ids go round-robin over the XCDs;
+// give each XCD a contiguous range of the (spatially ordered) work list so
+// its L2 holds one band of the grid.
+__device__ inline int xcd_remap(int bid, int nlaunch) {
+  const int per = nlaunch / MAX_XCD;     // nlaunch is a multiple of MAX_XCD
+  return (bid % MAX_XCD) * per + bid / MAX_XCD;
+}
+
+}  // namespace ppd

@@ -1,0 +1,387 @@
+"""ctypes binding of libppd (include/ppd.h), argument marshalling only.
+
+Torch tensors provide device memory and the stream; every operation runs in
+the HIP kernels of ``libppd.so``.  There is no fallback: if the library is
+missing, or no GPU is present, the calls raise.
+
+Shapes and dtypes are checked here, on the host, before any launch, because
+the C ABI takes plain pointers and cannot check buffer sizes itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libppd.so")
+
+# status codes and flags (include/ppd.h)
+PPD_OK, PPD_EINVAL, PPD_ENOMEM, PPD_EDEVICE, PPD_ENONFINITE, PPD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+USER_TO_PLAN, PLAN_TO_USER = 0, 1
+ORDER_PLAN, ORDER_USER = 0, 1
+SARA_ANALYSIS, SARA_SYNTHESIS, SARA_DUAL = 0, 1, 2
+FORM_FUSED, FORM_PLAIN = 0, 1
+
+c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("M", c_int64), ("d", c_int32),
+                ("block_off", ctypes.POINTER(c_int64)), ("omega_u", c_void_p), ("omega_v", c_void_p),
+                ("theta", c_void_p), ("kb_beta", c_double), ("levels", c_int32), ("tile", c_int32),
+                ("chunk", c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("Kx", c_int32), ("Ky", c_int32), ("M", c_int64),
+                ("d", c_int32), ("levels", c_int32), ("tile", c_int32), ("chunk", c_int32),
+                ("n_chunks", c_int32), ("kb_beta", c_double), ("device_bytes", ctypes.c_size_t)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("x", c_void_p), ("xt", c_void_p), ("v", c_void_p), ("u", c_void_p), ("z", c_void_p),
+                ("iter", c_int64)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tau", c_double), ("eta", c_double), ("zeta", c_double), ("lambda_", c_double),
+                ("alpha", c_double), ("mu", c_double), ("n_itr", c_int32), ("form", c_int32),
+                ("use_graph", c_int32), ("pad_", c_int32), ("y", c_void_p), ("U", c_void_p),
+                ("eps", ctypes.POINTER(c_double)), ("x_true", c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iter", c_int64), ("rel_change", c_double), ("x_norm", c_double), ("snr_db", c_double),
+                ("residual_max", c_double)]
+
+
+_PROTOS = {
+    "ppd_strerror": (ctypes.c_char_p, [c_int32]),
+    "ppd_last_error": (ctypes.c_char_p, []),
+    "ppd_plan_create": (c_int32, [ctypes.POINTER(c_void_p), ctypes.POINTER(PlanDesc), c_void_p]),
+    "ppd_plan_destroy": (c_int32, [c_void_p]),
+    "ppd_plan_set_stream": (c_int32, [c_void_p, c_void_p]),
+    "ppd_plan_get_info": (c_int32, [c_void_p, ctypes.POINTER(PlanInfo)]),
+    "ppd_plan_permutation": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
+    "ppd_plan_permute": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32]),
+    "ppd_phi": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
+    "ppd_phit": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
+    "ppd_sara": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float]),
+    "ppd_ellipsoid_proj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double),
+                                     c_int32, c_double, c_void_p]),
+    "ppd_uniform_weights": (c_int32, [c_void_p, c_void_p]),
+    "ppd_op_norm": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_double, ctypes.POINTER(c_double),
+                              ctypes.POINTER(c_int32)]),
+    "ppd_iterate": (c_int32, [c_void_p, ctypes.POINTER(State), ctypes.POINTER(Params), c_int32,
+                              ctypes.POINTER(Stats), ctypes.POINTER(c_double)]),
+    "ppd_timing_enable": (c_int32, [c_void_p, c_int32]),
+    "ppd_timing_reset": (c_int32, [c_void_p]),
+    "ppd_timing_read": (c_int32, [c_void_p, c_int32, ctypes.POINTER(ctypes.c_char_p),
+                                  ctypes.POINTER(c_int64), ctypes.POINTER(c_double), ctypes.POINTER(c_int32)]),
+    "ppd_kb_weights_host": (c_int32, [c_double, c_int64, c_void_p, c_void_p]),
+    "ppd_daubechies_host": (c_int32, [c_int32, ctypes.POINTER(c_double)]),
+}
+
+_lib = None
+
+
+def _hip_runtimes_mapped():
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64" in line:
+                paths.add(line.split()[-1])
+    return paths
+
+
+def lib() -> ctypes.CDLL:
+    """Load libppd.so (after torch, so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  -- loads torch's HIP runtime first
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1701_01748_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        rts = _hip_runtimes_mapped()
+        if len(rts) > 1:
+            raise RuntimeError(f"two HIP runtimes are mapped in this process: {sorted(rts)}")
+        _lib = L
+    return _lib
+
+
+class PPDError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        L = lib()
+        super().__init__(f"{fn}: {L.ppd_strerror(status).decode()} ({status}): {L.ppd_last_error().decode()}")
+        self.status = status
+
+
+def _check(fn: str, status: int):
+    if status != PPD_OK:
+        raise PPDError(fn, status)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _need(t, dtype, numel: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+class Plan:
+    """A libppd plan for one coverage (HOST numpy inputs, see ppd_plan_desc)."""
+
+    def __init__(self, nx: int, ny: int, omega_u, omega_v, block_off, theta=None, kb_beta: float = 0.0,
+                 levels: int = 3, tile: int = 0, chunk: int = 0, stream=None):
+        import torch
+        L = lib()
+        self._wu = np.ascontiguousarray(omega_u, dtype=np.float32)
+        self._wv = np.ascontiguousarray(omega_v, dtype=np.float32)
+        self._off = np.ascontiguousarray(block_off, dtype=np.int64)
+        self._th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float32)
+        if self._wu.shape != self._wv.shape or self._wu.ndim != 1:
+            raise ValueError("omega_u and omega_v must be equal-length 1-D arrays")
+        if self._th is not None and self._th.shape != self._wu.shape:
+            raise ValueError("theta must match omega")
+        desc = PlanDesc(nx, ny, self._wu.size, self._off.size - 1,
+                        self._off.ctypes.data_as(ctypes.POINTER(c_int64)),
+                        self._wu.ctypes.data, self._wv.ctypes.data,
+                        None if self._th is None else self._th.ctypes.data,
+                        kb_beta, levels, tile, chunk)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = c_void_p()
+        _check("ppd_plan_create", L.ppd_plan_create(ctypes.byref(h), ctypes.byref(desc),
+                                                    c_void_p(int(stream.cuda_stream))))
+        self._h = h
+        info = PlanInfo()
+        _check("ppd_plan_get_info", L.ppd_plan_get_info(h, ctypes.byref(info)))
+        self.info = info
+        self.nx, self.ny, self.M, self.d = nx, ny, int(info.M), int(info.d)
+        self.N = nx * ny
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().ppd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        _check("ppd_plan_set_stream", lib().ppd_plan_set_stream(self.handle, c_void_p(int(stream.cuda_stream))))
+        self.stream = stream
+
+    def permutation(self) -> np.ndarray:
+        out = np.empty(self.M, dtype=np.int64)
+        _check("ppd_plan_permutation", lib().ppd_plan_permutation(self.handle, out.ctypes.data_as(ctypes.POINTER(c_int64))))
+        return out
+
+    def permute(self, direction: int, t, out=None):
+        import torch
+        if t.numel() != self.M and t.dtype not in (torch.complex64, torch.complex128, torch.float64):
+            raise ValueError("per-visibility array expected")
+        eb = t.element_size()
+        if out is None:
+            out = torch.empty_like(t)
+        _need(t, t.dtype, self.M, "in")
+        _need(out, t.dtype, self.M, "out")
+        _check("ppd_plan_permute", lib().ppd_plan_permute(self.handle, direction, _ptr(t), _ptr(out), eb))
+        return out
+
+    # ---- timing ------------------------------------------------------------
+    def timing(self, on: bool):
+        _check("ppd_timing_enable", lib().ppd_timing_enable(self.handle, int(on)))
+
+    def timing_reset(self):
+        _check("ppd_timing_reset", lib().ppd_timing_reset(self.handle))
+
+    def timing_read(self) -> dict:
+        cap = 32
+        names = (ctypes.c_char_p * cap)()
+        counts = (c_int64 * cap)()
+        ms = (c_double * cap)()
+        n = c_int32()
+        _check("ppd_timing_read", lib().ppd_timing_read(self.handle, cap, names, counts, ms, ctypes.byref(n)))
+        return {names[i].decode(): (int(counts[i]), float(ms[i])) for i in range(min(n.value, cap))}
+
+
+def _alloc(shape, dtype, like=None):
+    import torch
+    return torch.empty(shape, dtype=dtype, device="cuda")
+
+
+def ppd_phi(plan: Plan, x, y=None, order: int = ORDER_PLAN):
+    """y = Theta G F Z x (complex64, plan or user order)."""
+    import torch
+    _need(x, torch.float32, plan.N, "x")
+    if y is None:
+        y = _alloc((plan.M,), torch.complex64)
+    _need(y, torch.complex64, plan.M, "y")
+    _check("ppd_phi", lib().ppd_phi(plan.handle, _ptr(x), _ptr(y), order))
+    return y
+
+
+def ppd_phit(plan: Plan, y, x=None, order: int = ORDER_PLAN):
+    """x = Re Phi^H y (float32 image)."""
+    import torch
+    _need(y, torch.complex64, plan.M, "y")
+    if x is None:
+        x = _alloc((plan.ny, plan.nx), torch.float32)
+    _need(x, torch.float32, plan.N, "x")
+    _check("ppd_phit", lib().ppd_phit(plan.handle, _ptr(y), _ptr(x), order))
+    return x
+
+
+def ppd_sara(plan: Plan, op: int, inp, out=None, u=None, alpha: float = 0.0, lam: float = 1.0):
+    import torch
+    if op == SARA_ANALYSIS:
+        _need(inp, torch.float32, plan.N, "in")
+        if out is None:
+            out = _alloc((9, plan.ny, plan.nx), torch.float32)
+        _need(out, torch.float32, 9 * plan.N, "out")
+    elif op == SARA_SYNTHESIS:
+        _need(inp, torch.float32, 9 * plan.N, "in")
+        if out is None:
+            out = _alloc((plan.ny, plan.nx), torch.float32)
+        _need(out, torch.float32, plan.N, "out")
+    elif op == SARA_DUAL:
+        _need(inp, torch.float32, plan.N, "in")
+        _need(u, torch.float32, 9 * plan.N, "u")
+        if out is None:
+            out = _alloc((plan.ny, plan.nx), torch.float32)
+        _need(out, torch.float32, plan.N, "out")
+    else:
+        raise ValueError("unknown SARA op")
+    _check("ppd_sara", lib().ppd_sara(plan.handle, op, _ptr(inp), _ptr(out), _ptr(u), float(alpha), float(lam)))
+    return out
+
+
+def _eps_arg(plan: Plan, eps):
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    if e.shape != (plan.d,):
+        raise ValueError(f"eps must have shape ({plan.d},)")
+    return e, e.ctypes.data_as(ctypes.POINTER(c_double))
+
+
+def ppd_ellipsoid_proj(plan: Plan, w, y, U, eps, n_itr: int, mu: float, z):
+    """n_itr Algorithm 2 iterations per block, in place on z (complex128)."""
+    import torch
+    _need(w, torch.complex128, plan.M, "w")
+    _need(y, torch.complex64, plan.M, "y")
+    _need(U, torch.float64, plan.M, "U")
+    _need(z, torch.complex128, plan.M, "z")
+    e, ep = _eps_arg(plan, eps)
+    _check("ppd_ellipsoid_proj", lib().ppd_ellipsoid_proj(plan.handle, _ptr(w), _ptr(y), _ptr(U), ep,
+                                                          int(n_itr), float(mu), _ptr(z)))
+    return z
+
+
+def ppd_uniform_weights(plan: Plan, U=None):
+    import torch
+    if U is None:
+        U = _alloc((plan.M,), torch.float64)
+    _need(U, torch.float64, plan.M, "U")
+    _check("ppd_uniform_weights", lib().ppd_uniform_weights(plan.handle, _ptr(U)))
+    return U
+
+
+def ppd_op_norm(plan: Plan, U, x0, max_iter: int = 1000, tol: float = 1e-10):
+    import torch
+    if U is not None:
+        _need(U, torch.float64, plan.M, "U")
+    _need(x0, torch.float32, plan.N, "x0")
+    out = c_double()
+    it = c_int32()
+    _check("ppd_op_norm", lib().ppd_op_norm(plan.handle, _ptr(U), _ptr(x0), int(max_iter), float(tol),
+                                            ctypes.byref(out), ctypes.byref(it)))
+    return float(out.value), int(it.value)
+
+
+class PPDState:
+    """Device state of Algorithm 3 (x, x tilde, v, u, z) owned by torch."""
+
+    def __init__(self, plan: Plan, y=None):
+        import torch
+        self.x = torch.zeros((plan.ny, plan.nx), dtype=torch.float32, device="cuda")
+        self.xt = torch.zeros_like(self.x)
+        self.v = torch.zeros(plan.M, dtype=torch.complex64, device="cuda")
+        self.u = torch.zeros((9, plan.ny, plan.nx), dtype=torch.float32, device="cuda")
+        self.z = torch.zeros(plan.M, dtype=torch.complex128, device="cuda")
+        if y is not None:
+            self.z.copy_(y.to(torch.complex128))
+        self.iter = 0
+
+    def clone(self):
+        c = object.__new__(PPDState)
+        for k in ("x", "xt", "v", "u", "z"):
+            setattr(c, k, getattr(self, k).clone())
+        c.iter = self.iter
+        return c
+
+
+def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49, eta=1.0, zeta=1.0,
+                lam=1.0, alpha=1e-4, mu=1.0, n_itr=1, form=FORM_FUSED, use_graph=False, x_true=None,
+                stats: bool = True):
+    """Run n_iter iterations of Algorithm 3; returns a statistics dict (or None)."""
+    import torch
+    _need(y, torch.complex64, plan.M, "y")
+    _need(U, torch.float64, plan.M, "U")
+    for k, dt, n in (("x", torch.float32, plan.N), ("xt", torch.float32, plan.N),
+                     ("v", torch.complex64, plan.M), ("u", torch.float32, 9 * plan.N),
+                     ("z", torch.complex128, plan.M)):
+        _need(getattr(state, k), dt, n, k)
+    if x_true is not None:
+        _need(x_true, torch.float32, plan.N, "x_true")
+    e, ep = _eps_arg(plan, eps)
+    st = State(_ptr(state.x), _ptr(state.xt), _ptr(state.v), _ptr(state.u), _ptr(state.z), state.iter)
+    prm = Params(tau, eta, zeta, lam, alpha, mu, n_itr, form, int(use_graph), 0, _ptr(y), _ptr(U), ep,
+                 _ptr(x_true))
+    out = Stats()
+    res = (c_double * plan.d)()
+    _check("ppd_iterate", lib().ppd_iterate(plan.handle, ctypes.byref(st), ctypes.byref(prm), int(n_iter),
+                                            ctypes.byref(out) if stats else None, res if stats else None))
+    state.iter = int(st.iter)
+    if not stats:
+        return None
+    return {"iter": int(out.iter), "rel_change": out.rel_change, "x_norm": out.x_norm,
+            "snr_db": out.snr_db, "residual_max": out.residual_max, "residual": np.array(res[:])}
+
+
+def kb_weights_host(s, kb_beta: float = 0.0) -> np.ndarray:
+    s = np.ascontiguousarray(s, dtype=np.float32)
+    w = np.empty((s.size, 8), dtype=np.float32)
+    _check("ppd_kb_weights_host", lib().ppd_kb_weights_host(kb_beta, s.size, s.ctypes.data, w.ctypes.data))
+    return w
+
+
+def daubechies_host(p: int) -> np.ndarray:
+    h = np.empty(2 * p, dtype=np.float64)
+    _check("ppd_daubechies_host", lib().ppd_daubechies_host(p, h.ctypes.data_as(ctypes.POINTER(c_double))))
+    return h

@@ -1,0 +1,116 @@
+"""GPU parity of Algorithm 3 (ppd_iterate) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ppd as O
+from oracle import problem as oprob
+from oracle import prox as oprox
+
+from gpu_util import announce, assert_op_close, dev, host, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_problem(seed=11, n=64, M=6000, d=3):
+    x, wu, wv, off = synth.small_case(n, M, seed=seed, d=d)
+    noise = synth.noise_unit(M, 200 + seed)
+    pb = oprob.make_problem(x, wu, wv, off, noise, 30.0, np.ones((n, n)), power_tol=1e-8)
+    return pb, wu, wv
+
+
+def _gpu_inputs(P, plan, pb):
+    import torch
+    perm = plan.permutation()
+    y = dev(pb.y[perm].astype(np.complex64), torch.complex64)
+    U = dev(pb.U[perm], torch.float64)
+    return perm, y, U
+
+
+@pytest.mark.parametrize("form", ["fused", "plain"])
+@pytest.mark.parametrize("n_itr", [1, 3])
+def test_iterations_match_oracle(form, n_itr):
+    P = require_gpu()
+    import torch
+    announce(f"ppd iterate small form={form} n_itr={n_itr}")
+    pb, wu, wv = _small_problem()
+    n = pb.x_true.shape[0]
+    plan = P.Plan(n, n, wu, wv, pb.block_off, chunk=300)
+    perm, y, U = _gpu_inputs(P, plan, pb)
+    st = P.PPDState(plan, y)
+    prm = O.Params(eta=pb.eta, mu=1.0, n_itr=n_itr)
+    ost = O.init_state(n, n, pb.y)
+    f = P.FORM_FUSED if form == "fused" else P.FORM_PLAIN
+    for T in (1, 4):
+        O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, ost, T)
+        s = P.ppd_iterate(plan, st, y, U, pb.eps, T, eta=pb.eta, mu=1.0, n_itr=n_itr, form=f)
+        assert s["iter"] == ost.it
+        assert_op_close(host(st.x), ost.x, what=f"x after {ost.it}")
+        assert_op_close(host(st.xt), ost.xt, what=f"x tilde after {ost.it}")
+        assert_op_close(host(st.v), ost.v[perm], what=f"v after {ost.it}")
+        assert_op_close(host(st.z), ost.z[perm], what=f"z after {ost.it}")
+        assert_op_close(host(st.u), ost.u, what=f"u after {ost.it}")
+
+
+def test_first_iteration_closed_form_gpu():
+    P = require_gpu()
+    announce("first iteration closed form")
+    pb, wu, wv = _small_problem(seed=12)
+    n = pb.x_true.shape[0]
+    plan = P.Plan(n, n, wu, wv, pb.block_off)
+    perm, y, U = _gpu_inputs(P, plan, pb)
+    st = P.PPDState(plan, y)
+    P.ppd_iterate(plan, st, y, U, pb.eps, 1, eta=pb.eta, mu=1.0)
+    z = np.empty_like(pb.y)
+    for j in range(len(pb.eps)):
+        s = slice(pb.block_off[j], pb.block_off[j + 1])
+        z[s] = oprox.proj_B((1 - pb.U[s]) * pb.y[s], pb.y[s], pb.eps[j])
+    x1 = np.maximum(0.49 * pb.eta * pb.op.phit(pb.U * z), 0.0)
+    assert_op_close(host(st.x), x1, what="x1")
+    assert_op_close(host(st.xt), 2 * x1, what="x tilde 1")
+    assert np.abs(host(st.u)).max() == 0.0
+
+
+def test_graph_replay_matches_eager():
+    P = require_gpu()
+    import torch
+    announce("graph replay vs eager")
+    pb, wu, wv = _small_problem(seed=13)
+    n = pb.x_true.shape[0]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = P.Plan(n, n, wu, wv, pb.block_off, stream=stream)
+        perm, y, U = _gpu_inputs(P, plan, pb)
+        a = P.PPDState(plan, y)
+        b = P.PPDState(plan, y)
+        for rep in range(3):   # replays with eager work in between
+            P.ppd_iterate(plan, a, y, U, pb.eps, 5, eta=pb.eta, use_graph=False)
+            P.ppd_iterate(plan, b, y, U, pb.eps, 5, eta=pb.eta, use_graph=True)
+            stream.synchronize()
+            assert rel_err(host(b.x), host(a.x)) < 1e-6, rep
+            assert rel_err(host(b.v), host(a.v)) < 1e-6, rep
+
+
+def test_workload64_snr_parity():
+    """200 PPD and PD iterations on the 64x64 workload: SNR within 0.05 dB."""
+    P = require_gpu()
+    import torch
+    w = synth.WORKLOADS["ppd64"]
+    inp = synth.make_inputs(w)
+    pb = oprob.problem_from_inputs(inp, power_tol=1e-9)
+    plan = P.Plan(64, 64, inp.wu[0], inp.wv[0], inp.block_off)
+    perm, y, U = _gpu_inputs(P, plan, pb)
+    xt = dev(pb.x_true.astype(np.float32), torch.float32)
+    for name, Uo, eta in [("ppd", pb.U, pb.eta), ("pd", np.ones_like(pb.U), pb.eta_pd)]:
+        announce(f"workload64 {name} 200 iterations")
+        ost = O.init_state(64, 64, pb.y)
+        h = O.iterate(pb.op, pb.y, Uo, pb.eps, pb.block_off, O.Params(eta=eta, mu=1.0 / Uo.max()), ost, 200,
+                      x_true=pb.x_true)
+        st = P.PPDState(plan, y)
+        Ud = U if name == "ppd" else dev(np.ones(pb.U.size), torch.float64)
+        snr = []
+        for k in range(20):
+            s = P.ppd_iterate(plan, st, y, Ud, pb.eps, 10, eta=eta, mu=1.0, x_true=xt)
+            snr.append(s["snr_db"])
+            assert abs(s["snr_db"] - h[10 * k + 9]["snr"]) < 0.05, (name, k, s["snr_db"], h[10 * k + 9]["snr"])
+        assert rel_err(host(st.x), ost.x) < 1e-3
