@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the PPD hot path on one MI355X.
+
+Workload (default): 512 x 512 image, M = 1.3M visibilities on a 1/r-dense
+radial coverage in 16 uneven blocks (20k..200k), 30 dB input SNR, SARA with
+3 levels, one Algorithm 2 sub-iteration.  A step is one full iteration of
+Algorithm 3 (forward FFT, degridding with the fused dual update, gridding,
+inverse FFT, SARA analysis + dual clip + synthesis, primal update), replayed
+from a captured HIP graph, inputs resident in HBM.
+
+Prints one JSON line: PPD iterations/s (value), Phi / Phi^H visibilities/s,
+the plain (unfused, per-block FP64) form for comparison, the roofline of the
+dominant kernel (per-launch HIP events) and the FP64 oracle timed on the
+host's cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PPD iters/s + Phi/Phi^T vis/s at 512^2, M=1.3M; batched vs plain, HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(kind: str, M: int, N: int, K: int, ny: int, Kx: int) -> float:
+    """Bytes each kernel kind must move per launch (fused PPD iteration)."""
+    if kind == "degrid":      # omega 8, v 8, U 8, z 16, y 8 in; w 16 out; grid read once
+        return 64.0 * M + 8.0 * K
+    if kind == "grid":        # omega 8, w 16, z 16, U 8, y 8, v 8 in; z 16, v 8 out; grid written once
+        return 88.0 * M + 8.0 * K
+    if kind == "fft_rows_fwd":
+        return 4.0 * N + 8.0 * ny * Kx
+    if kind in ("fft_cols_fwd", "fft_cols_inv"):
+        return 8.0 * ny * Kx + 8.0 * K
+    if kind == "fft_rows_inv":  # half in; x, u~ in; x, x~ out
+        return 8.0 * ny * Kx + 16.0 * N
+    if kind == "zero":
+        return 8.0 * K
+    if kind == "dwt":          # per level on average: x / low-pass in, 9 duals read+written
+        return (4.0 * N + 72.0 * N) / 3.0
+    if kind == "idwt":
+        return (36.0 * N + 4.0 * N) / 3.0
+    return 0.0
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="ppd512")
+    ap.add_argument("--n-itr", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--quick", action="store_true", help="skip the secondary measurements (profiling runs)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE={world})", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1701_01748_amd import ppd as P
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    w = synth.WORKLOADS[args.workload]
+    inp = synth.make_inputs(w)
+    n = w.n
+    wu, wv, off = inp.wu[0], inp.wv[0], inp.block_off
+    M, N = w.M, n * n
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    plan = P.Plan(n, n, wu, wv, off, stream=stream)
+    info = plan.info
+    K, Kx = info.Kx * info.Ky, info.Kx
+    perm = plan.permutation()
+
+    # ---- problem setup on the GPU (not timed) --------------------------------
+    U = P.ppd_uniform_weights(plan)
+    x_true = torch.as_tensor(inp.x_true.astype(np.float32)).cuda()
+    y0 = P.ppd_phi(plan, x_true)
+    sigma = math.sqrt(float((y0.abs().double() ** 2).sum()) / M * 10.0 ** (-w.isnr_db / 10.0))
+    noise = torch.as_tensor(inp.noise[0][perm].astype(np.complex64)).cuda()
+    y = (y0 + sigma * noise).contiguous()
+    Mj = np.diff(off).astype(np.float64)
+    eps = sigma * np.sqrt(Mj + 2.0 * np.sqrt(Mj))
+    norm2, it_pow = P.ppd_op_norm(plan, U, torch.as_tensor(inp.power_start.astype(np.float32)).cuda(),
+                                  300, 1e-7)
+    eta = 1.0 / norm2
+    kw = dict(eta=eta, tau=0.49, zeta=1.0, lam=1.0, alpha=1e-4, mu=1.0, n_itr=args.n_itr)
+    state = P.PPDState(plan, y)
+
+    # ---- timed region: graph replay of the fused iteration ---------------------
+    P.ppd_iterate(plan, state, y, U, eps, args.warmup, use_graph=True, stats=False, **kw)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    P.ppd_iterate(plan, state, y, U, eps, args.steps, use_graph=True, stats=False, **kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall_s = t1 - t0
+    ev_ms = e0.elapsed_time(e1)
+    value = args.steps / wall_s
+    st = P.ppd_iterate(plan, state, y, U, eps, 1, use_graph=True, x_true=x_true, **kw)
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "PPD iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000.0 * wall_s / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "image": f"{n}x{n}", "M": M, "blocks": int(len(off) - 1),
+                   "n_itr": args.n_itr, "levels": 3, "form": "fused, hip graph", "tile": info.tile,
+                   "chunk": info.chunk},
+        "event_ms_per_step": round(ev_ms / args.steps, 4),
+        "snr_db_after": round(st["snr_db"], 3), "iterations_done": st["iter"],
+        "residual_max_over_eps": round(st["residual_max"], 4),
+        "op_norm_power_iters": it_pow,
+    }
+
+    # ---- per-kernel HIP events: eager pass of the same iteration ------------------
+    n_prof = 10
+    plan.timing(True)
+    plan.timing_reset()
+    P.ppd_iterate(plan, state, y, U, eps, n_prof, use_graph=False, stats=False, **kw)
+    tk = plan.timing_read()
+    plan.timing(False)
+    per_kind = {k: {"launches": c, "avg_us": round(1000.0 * ms / c, 3)} for k, (c, ms) in tk.items()}
+    dom = max(tk.items(), key=lambda kv: kv[1][1])[0]
+    cnt, ms = tk[dom]
+    avg_s = ms / cnt / 1000.0
+    algo = algorithmic_bytes(dom, M, N, K, n, Kx)
+    achieved = algo / avg_s / 1e9
+    out["kernels"] = per_kind
+    out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                       "algorithmic_bytes_per_launch": algo, "avg_launch_us": round(avg_s * 1e6, 3)}
+
+    if not args.quick:
+        # ---- Phi / Phi^H visibilities per second (plan order) ------------------------
+        def time_calls(fn, reps=30):
+            for _ in range(3):
+                fn()
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            return sorted(ts)[len(ts) // 2] / 1000.0
+
+        yb = torch.empty(M, dtype=torch.complex64, device="cuda")
+        xb = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        t_phi = time_calls(lambda: P.ppd_phi(plan, x_true, yb))
+        t_phit = time_calls(lambda: P.ppd_phit(plan, y, xb))
+        phi_bytes = 4.0 * N + 16.0 * M + 8.0 * n * Kx + 16.0 * K
+        out["phi_vis_per_s"] = round(M / t_phi, 1)
+        out["phit_vis_per_s"] = round(M / t_phit, 1)
+        out["phi_us"] = round(t_phi * 1e6, 2)
+        out["phit_us"] = round(t_phit * 1e6, 2)
+        out["phi_algorithmic_GBps"] = round(phi_bytes / t_phi / 1e9, 1)
+        out["phit_algorithmic_GBps"] = round(phi_bytes / t_phit / 1e9, 1)
+
+        # ---- batched (fused) eager and plain per-block FP64 forms --------------------
+        def iters_per_s(form, graph, T):
+            s2 = state.clone()
+            P.ppd_iterate(plan, s2, y, U, eps, 2, form=form, use_graph=graph, stats=False, **kw)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            P.ppd_iterate(plan, s2, y, U, eps, T, form=form, use_graph=graph, stats=False, **kw)
+            torch.cuda.synchronize()
+            return T / (time.perf_counter() - ta)
+
+        out["fused_eager_iters_per_s"] = round(iters_per_s(P.FORM_FUSED, False, 50), 2)
+        out["plain_iters_per_s"] = round(iters_per_s(P.FORM_PLAIN, False, 20), 2)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inp, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(inp, iters: int) -> dict:
+    """The FP64 oracle (untuned) timed on the host on a bounded sample:
+    `iters` full PPD iterations of the same workload, setup excluded."""
+    import numpy as np
+
+    from oracle import nufft as onf
+    from oracle import ppd as O
+    from oracle import problem as oprob
+
+    w = inp.workload
+    wu, wv, off = inp.wu[0], inp.wv[0], inp.block_off
+    op = onf.Nufft(wu, wv, w.n, w.n)
+    y0 = op.phi(inp.x_true)
+    sigma = math.sqrt(np.sum(np.abs(y0) ** 2) / w.M * 10.0 ** (-w.isnr_db / 10.0))
+    y = (y0 + sigma * inp.noise[0]).astype(np.complex64).astype(np.complex128)
+    U = oprob.uniform_weights(wu, wv, w.n, w.n)
+    eps = oprob.l2_bounds(sigma, off)
+    # the step size value does not change the arithmetic being timed
+    prm = O.Params(eta=1e-3, mu=1.0, n_itr=1)
+    st = O.init_state(w.n, w.n, y)
+    t0 = time.perf_counter()
+    O.iterate(op, y, U, eps, off, prm, st, iters)
+    dt = time.perf_counter() - t0
+    return {"value": round(iters / dt, 5), "unit": "PPD iterations/s", "cores": 1, "kind": "oracle",
+            "host_cpus": os.cpu_count(),
+            "sample": f"{iters} full FP64 oracle iterations of {w.name} (setup excluded), "
+                      f"{dt:.1f} s; NumPy/SciPy single-threaded"}
+
+
+if __name__ == "__main__":
+    main()

@@ -20,66 +20,50 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-__device__ inline double block_norm2(int j, const double* __restrict__ part,
-                                     const int32_t* __restrict__ bids, const int32_t* __restrict__ boff) {
-  const int lane = threadIdx.x & 63;
-  double s = 0.0;
-  for (int c = boff[j] + lane; c < boff[j + 1]; c += 64) s += part[bids[c]];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  return s;
-}
-
-// One Algorithm 2 iteration over every block, chunk by chunk.
+// One Algorithm 2 iteration over every block, item by item.
 //   mode 0: partials of ||q - y||^2, q = z - mu U (z - w)   (z unchanged)
-//   mode 1: z <- P_B(q) with the norms in part_in, then partials of the next q
+//   mode 1: z <- P_B(q) with the block factors, then partials of the next q
 //   mode 2: z <- P_B(q) only
 __global__ __launch_bounds__(256) void k_alg2(
-    int mode, const Chunk* __restrict__ chunks, int n_chunks, const double2* __restrict__ w,
-    const float2* __restrict__ y, const double* __restrict__ U, double2* __restrict__ z, double mu,
-    const double* __restrict__ part_in, double* __restrict__ part_out,
-    const int32_t* __restrict__ bids, const int32_t* __restrict__ boff, const double* __restrict__ eps) {
-  __shared__ double s_fac;
-  __shared__ int s_inside;
+    int mode, const Item* __restrict__ items, int n_items, const Seg* __restrict__ segs,
+    const double2* __restrict__ w, const float2* __restrict__ y, const double* __restrict__ U,
+    double2* __restrict__ z, double mu, const double* __restrict__ bfac,
+    const int32_t* __restrict__ binside, double* __restrict__ part_out) {
   __shared__ double red[16];
-  const int ci = xcd_remap(blockIdx.x, gridDim.x);
-  if (ci >= n_chunks) return;
-  const Chunk ch = chunks[ci];
-  if (mode != 0 && threadIdx.x < 64) {
-    const double r = sqrt(block_norm2(ch.block, part_in, bids, boff));
-    if (threadIdx.x == 0) {
-      const double e = eps[ch.block];
-      s_inside = r <= e;
-      s_fac = r > e ? e / r : 1.0;
-    }
-  }
-  __syncthreads();
-  double qn = 0.0;
-  for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
-    const int pi = ch.start + k;
-    const double2 we = w[pi];
-    double2 ze = z[pi];
-    const double mU = mu * U[pi];
-    const float2 ye = y[pi];
+  const int ii = xcd_remap(blockIdx.x, gridDim.x);
+  if (ii >= n_items) return;
+  const Item it = items[ii];
+  for (int s = it.seg0; s < it.seg1; ++s) {
+    const Seg sg = segs[s];
+    double fac = 1.0;
+    bool inside = true;
     if (mode != 0) {
-      const double qx = ze.x - mU * (ze.x - we.x), qy = ze.y - mU * (ze.y - we.y);
-      if (!s_inside) {
-        ze.x = double(ye.x) + (qx - double(ye.x)) * s_fac;
-        ze.y = double(ye.y) + (qy - double(ye.y)) * s_fac;
-      } else {
-        ze.x = qx;
-        ze.y = qy;
+      fac = bfac[sg.block];
+      inside = binside[sg.block] != 0;
+    }
+    double qn = 0.0;
+    for (int k = threadIdx.x; k < sg.count; k += blockDim.x) {
+      const int pi = sg.start + k;
+      const double2 we = w[pi];
+      double2 ze = z[pi];
+      const double mU = mu * U[pi];
+      const float2 ye = y[pi];
+      if (mode != 0) {
+        const double qx = ze.x - mU * (ze.x - we.x), qy = ze.y - mU * (ze.y - we.y);
+        ze.x = inside ? qx : double(ye.x) + (qx - double(ye.x)) * fac;
+        ze.y = inside ? qy : double(ye.y) + (qy - double(ye.y)) * fac;
+        z[pi] = ze;
       }
-      z[pi] = ze;
+      if (mode != 2) {
+        const double dx = (ze.x - mU * (ze.x - we.x)) - double(ye.x);
+        const double dy = (ze.y - mU * (ze.y - we.y)) - double(ye.y);
+        qn += dx * dx + dy * dy;
+      }
     }
     if (mode != 2) {
-      const double dx = (ze.x - mU * (ze.x - we.x)) - double(ye.x);
-      const double dy = (ze.y - mU * (ze.y - we.y)) - double(ye.y);
-      qn += dx * dx + dy * dy;
+      qn = block_sum(qn, red);
+      if (threadIdx.x == 0) part_out[s] = qn;
     }
-  }
-  if (mode != 2) {
-    qn = block_sum(qn, red);
-    if (threadIdx.x == 0) part_out[ci] = qn;
   }
 }
 
@@ -211,10 +195,11 @@ int grid_blocks(int64_t n) { return int(std::min<int64_t>((n + PL_THREADS - 1) /
 
 int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* y, const double* U, double2* z,
                 double mu, const double* part_in, double* part_out) {
+  if (mode != 0) PPD_TRY(block_scale(p, part_in));
   int slot;
   PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
-  hipLaunchKernelGGL(k_alg2, dim3(p->n_launch), dim3(256), 0, p->stream, mode, p->chunks, p->n_chunks,
-                     w, y, U, z, mu, part_in, part_out, p->bchunk_ids, p->bchunk_off_d, p->eps_d);
+  hipLaunchKernelGGL(k_alg2, dim3(p->n_launch), dim3(256), 0, p->stream, mode, p->items, p->n_items,
+                     p->segs, w, y, U, z, mu, p->bfac, p->binside, part_out);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }
@@ -259,7 +244,7 @@ extern "C" int ppd_ellipsoid_proj(ppd_plan* p, const double* w, const float* y, 
   const float2* y2 = reinterpret_cast<const float2*>(y);
   double2* z2 = reinterpret_cast<double2*>(zbar);
   double* pa = p->part;
-  double* pb = p->part + p->n_chunks;
+  double* pb = p->part + p->n_segs;
   PPD_TRY(alg2_launch(p, 0, w2, y2, U, z2, mu, nullptr, pa));
   for (int s = 1; s < n_itr; ++s) {
     PPD_TRY(alg2_launch(p, 1, w2, y2, U, z2, mu, pa, pb));

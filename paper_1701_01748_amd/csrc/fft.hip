@@ -229,11 +229,6 @@ __global__ void k_fft_rows_inv(const float2* __restrict__ half, const float2* __
   }
 }
 
-__global__ void k_zero(float4* __restrict__ g, size_t n4) {
-  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n4; i += size_t(gridDim.x) * blockDim.x)
-    g[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-}
-
 struct RowCfg { int rpb, threads, blocks; size_t lds; };
 struct ColCfg { int C, threads, ngroups, blocks; size_t lds; };
 
@@ -314,15 +309,5 @@ int fft_rows_inverse_primal(ppd_plan* p, const PrimalArgs& a) {
 }
 
 int primal_partial_count(ppd_plan* p) { return row_cfg(p->Kx, p->ny).blocks; }
-
-int zero_grid(ppd_plan* p, float2* g) {
-  int slot;
-  const size_t n4 = size_t(p->Kx) * p->Ky / 2;
-  PPD_TRY(timer_begin(p, KK_ZERO, &slot));
-  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, p->stream, reinterpret_cast<float4*>(g), n4);
-  PPD_HIP(hipGetLastError());
-  PPD_TRY(timer_end(p, slot));
-  return PPD_OK;
-}
 
 }  // namespace ppd

@@ -126,9 +126,8 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
   const float* xt = c.primal.xt;
   PPD_TRY(fft_forward(p, xt));                              // step 4: a = F Z x~
   if (c.form == PPD_FORM_FUSED) {
-    PPD_TRY(zero_grid(p, p->grid_a));
     double* pa = p->part;
-    double* pb = p->part + p->n_chunks;
+    double* pb = p->part + p->n_segs;
     PPD_TRY(degrid_dual(p, c.dual, pa));                    // step 10 argument, first Alg. 2 step
     for (int s = 1; s < c.dual.n_itr; ++s) {
       PPD_TRY(alg2_launch(p, 1, p->wbuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb));
@@ -138,7 +137,6 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
   } else {
     PPD_TRY(degrid_plain(p, p->ybuf));
     PPD_TRY(plain_dual(p, c.dual));                         // steps 10-11, block by block
-    PPD_TRY(zero_grid(p, p->grid_a));
     PPD_TRY(grid_plain(p, c.dual.v));                       // step 12
   }
   PPD_TRY(fft_cols_inverse(p));
@@ -163,7 +161,7 @@ int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq) {
   int slot;
   PPD_TRY(timer_begin(p, KK_STATS, &slot));
   hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, p->stream, p->ppart, primal_partial_count(p), p->rpart,
-                     p->bchunk_ids, p->bchunk_off_d, p->res_sq, use_res_sq, p->eps_d, p->d, has_truth,
+                     p->bseg_ids, p->bseg_off_d, p->res_sq, use_res_sq, p->eps_d, p->d, has_truth,
                      p->stats_d);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
@@ -281,7 +279,6 @@ extern "C" int ppd_op_norm(ppd_plan* p, const double* U, const float* x0, int ma
                          p->stream, p->ybuf, U, p->M);
       PPD_HIP(hipGetLastError());
     }
-    PPD_TRY(zero_grid(p, p->grid_a));
     PPD_TRY(grid_plain(p, p->ybuf));
     PPD_TRY(fft_adjoint(p, p->img_tmp));
     PPD_TRY(img_norm(p, p->img_tmp, &lam));

@@ -1,17 +1,23 @@
 // Interpolation G and its adjoint (Sec. 2; Sec. 5: 8x8 Kaiser-Bessel
 // kernels), with the data-block dual update of Algorithm 3 fused in.
 //
-// Work unit: a chunk of <= chunk_max visibilities of one data block whose
-// first tap lies in one T x T grid tile.  The workgroup stages the tile
-// plus its 7-cell halo ((T+7)^2 complex cells) in LDS:
-//   degrid: the forward spectrum region is copied in, every thread then
+// Work item: up to chunk_max visibilities whose first tap lies in one
+// T x T grid tile, as per-block segments.  The workgroup works on the tile
+// plus its 7-cell halo, (T+7)^2 complex cells, in LDS:
+//   degrid: the forward spectrum region is copied in, each thread then
 //           interpolates its visibilities from LDS (64 taps each);
-//   grid:   contributions accumulate in LDS with ds_add_f32 and the region
-//           is added to the global grid once per chunk (no global atomics
-//           in the per-visibility loop).
+//   grid:   each wave owns a private copy of the region; a batch of 64
+//           visibilities is prepared one per lane (weights to LDS), then
+//           applied one visibility at a time with lane (a, b) owning tap
+//           (a, b), so a wave's 64 read-modify-writes never collide and no
+//           atomics are needed.  The wave copies are summed and stored to a
+//           per-item scratch slot; a fold pass then sums, for
+//           every grid cell, the slots of the owning tile and the halos of
+//           its left / upper / upper-left neighbours.  No global atomics,
+//           no zeroing pass, and a fixed summation order across items.
 // The 8 per-axis weights are evaluated on the fly from degree-9
-// polynomials; only the two float32 frequencies are read per visibility.
-// Chunks are launched in spatial order with an XCD-aware remap.
+// polynomials, so only the two float32 frequencies are read per visibility.
+// Items are launched in spatial order through an XCD-aware remap.
 #include "ppd_internal.h"
 
 namespace ppd {
@@ -47,183 +53,263 @@ __device__ __forceinline__ void taps_for(float omu, float omv, double su, double
   kb_weights(float(tv - fv), coef, t.wy);
 }
 
-// Norm of one data block's residual from its chunk partials (wave 0,
-// fixed order, so every workgroup of the block gets the same value).
-__device__ inline double block_norm2(int j, const double* __restrict__ part,
-                                     const int32_t* __restrict__ bids, const int32_t* __restrict__ boff) {
-  const int lane = threadIdx.x & 63;
-  double s = 0.0;
-  for (int c = boff[j] + lane; c < boff[j + 1]; c += 64) s += part[bids[c]];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  return s;
-}
-
 template <int T, bool DUAL>
 __global__ __launch_bounds__(256) void k_degrid(
-    const float2* __restrict__ grid, int Kx, int Ky, const Chunk* __restrict__ chunks, int n_chunks,
-    const float* __restrict__ wu, const float* __restrict__ wv, const float* __restrict__ theta,
-    double su, double sv, const float* __restrict__ kbc, float2* __restrict__ out,
-    const float2* __restrict__ y, const double* __restrict__ U, const float2* __restrict__ v,
-    const double2* __restrict__ z, double2* __restrict__ wout, double mu,
+    const float2* __restrict__ grid, int Kx, int Ky, const Item* __restrict__ items, int n_items,
+    const Seg* __restrict__ segs, const float* __restrict__ wu, const float* __restrict__ wv,
+    const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
+    float2* __restrict__ out, const float2* __restrict__ y, const double* __restrict__ U,
+    const float2* __restrict__ v, const double2* __restrict__ z, double2* __restrict__ wout, double mu,
     double* __restrict__ part, double* __restrict__ rpart) {
   constexpr int R = T + 7;
   __shared__ float2 reg[R * R];
   __shared__ float coef[KB_TAPS * KB_NC];
   __shared__ double red[16];
-  const int ci = xcd_remap(blockIdx.x, gridDim.x);
-  if (ci >= n_chunks) return;
-  const Chunk ch = chunks[ci];
-  const int r0 = ch.ty * T, c0 = ch.tx * T;
+  const int ii = xcd_remap(blockIdx.x, gridDim.x);
+  if (ii >= n_items) return;
+  const Item it = items[ii];
+  const int r0 = it.ty * T, c0 = it.tx * T;
   for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
     const int a = i / R, b = i - a * R;
     reg[i] = grid[size_t((r0 + a) & (Ky - 1)) * Kx + ((c0 + b) & (Kx - 1))];
   }
   if (threadIdx.x < KB_TAPS * KB_NC) coef[threadIdx.x] = kbc[threadIdx.x];
   __syncthreads();
-  double qn = 0.0, rn = 0.0;
-  for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
-    const int pi = ch.start + k;
-    Taps t;
-    taps_for<T>(wu[pi], wv[pi], su, sv, Kx, Ky, c0, r0, coef, t);
-    float ax = 0.f, ay = 0.f;
+  for (int s = it.seg0; s < it.seg1; ++s) {
+    const Seg sg = segs[s];
+    double qn = 0.0, rn = 0.0;
+    for (int k = threadIdx.x; k < sg.count; k += blockDim.x) {
+      const int pi = sg.start + k;
+      Taps t;
+      taps_for<T>(wu[pi], wv[pi], su, sv, Kx, Ky, c0, r0, coef, t);
+      float ax = 0.f, ay = 0.f;
 #pragma unroll
-    for (int a = 0; a < KB_TAPS; ++a) {
-      const float2* row = reg + (t.ov + a) * R + t.ou;
-      float sx = 0.f, sy = 0.f;
+      for (int a = 0; a < KB_TAPS; ++a) {
+        const float2* row = reg + (t.ov + a) * R + t.ou;
+        float sx = 0.f, sy = 0.f;
 #pragma unroll
-      for (int b = 0; b < KB_TAPS; ++b) {
-        const float2 g = row[b];
-        sx = fmaf(t.wx[b], g.x, sx);
-        sy = fmaf(t.wx[b], g.y, sy);
+        for (int b = 0; b < KB_TAPS; ++b) {
+          const float2 g = row[b];
+          sx = fmaf(t.wx[b], g.x, sx);
+          sy = fmaf(t.wx[b], g.y, sy);
+        }
+        ax = fmaf(t.wy[a], sx, ax);
+        ay = fmaf(t.wy[a], sy, ay);
       }
-      ax = fmaf(t.wy[a], sx, ax);
-      ay = fmaf(t.wy[a], sy, ay);
+      const float th = theta ? theta[pi] : 1.0f;
+      const float2 g = make_float2(ax * th, ay * th);
+      if (!DUAL) {
+        out[pi] = g;
+      } else {
+        // Algorithm 3 step 10: w = U^-1 v + Theta G a; first Algorithm 2 step
+        const float2 ve = v[pi];
+        const double Ue = U[pi];
+        const double2 ze = z[pi];
+        const float2 ye = y[pi];
+        const double wx = double(ve.x) / Ue + double(g.x);
+        const double wy = double(ve.y) / Ue + double(g.y);
+        wout[pi] = make_double2(wx, wy);
+        const double mU = mu * Ue;
+        const double dx = (ze.x - mU * (ze.x - wx)) - double(ye.x);
+        const double dy = (ze.y - mU * (ze.y - wy)) - double(ye.y);
+        qn += dx * dx + dy * dy;
+        const double ex = double(g.x) - double(ye.x), ey = double(g.y) - double(ye.y);
+        rn += ex * ex + ey * ey;
+      }
     }
-    const float th = theta ? theta[pi] : 1.0f;
-    const float2 g = make_float2(ax * th, ay * th);
-    if (!DUAL) {
-      out[pi] = g;
-    } else {
-      // Algorithm 3 step 10: w = U^-1 v + Theta G a; first Algorithm 2 step
-      const float2 ve = v[pi];
-      const double Ue = U[pi];
-      const double2 ze = z[pi];
-      const float2 ye = y[pi];
-      const double wx = double(ve.x) / Ue + double(g.x);
-      const double wy = double(ve.y) / Ue + double(g.y);
-      wout[pi] = make_double2(wx, wy);
-      const double mU = mu * Ue;
-      const double dx = (ze.x - mU * (ze.x - wx)) - double(ye.x);
-      const double dy = (ze.y - mU * (ze.y - wy)) - double(ye.y);
-      qn += dx * dx + dy * dy;
-      const double ex = double(g.x) - double(ye.x), ey = double(g.y) - double(ye.y);
-      rn += ex * ex + ey * ey;
-    }
-  }
-  if (DUAL) {
-    qn = block_sum(qn, red);
-    rn = block_sum(rn, red);
-    if (threadIdx.x == 0) {
-      part[ci] = qn;
-      rpart[ci] = rn;
+    if (DUAL) {
+      qn = block_sum(qn, red);
+      rn = block_sum(rn, red);
+      if (threadIdx.x == 0) {
+        part[s] = qn;
+        rpart[s] = rn;
+      }
     }
   }
 }
 
-// Alg. 2 projection: z' = P_B(q) with the block's scale factor.
-__device__ __forceinline__ void project(double qx, double qy, float2 ye, bool inside, double f,
-                                        double& zx, double& zy) {
-  if (inside) {
-    zx = qx;
-    zy = qy;
-  } else {
-    zx = double(ye.x) + (qx - double(ye.x)) * f;
-    zy = double(ye.y) + (qy - double(ye.y)) * f;
-  }
+// Waves per gridding workgroup: each wave owns a private copy of the
+// (T+7)^2 region in LDS.
+template <int T>
+struct GridCfg {
+  static constexpr int R = T + 7;
+  static constexpr int NW = (T >= 64) ? 2 : 4;
+  static constexpr int THREADS = NW * 64;
+};
+
+__device__ __forceinline__ float lane_f(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
 
 template <int T, bool DUAL>
-__global__ __launch_bounds__(256) void k_grid(
-    float2* __restrict__ grid, int Kx, int Ky, const Chunk* __restrict__ chunks, int n_chunks,
-    const float* __restrict__ wu, const float* __restrict__ wv, const float* __restrict__ theta,
-    double su, double sv, const float* __restrict__ kbc, const float2* __restrict__ vin,
-    const float2* __restrict__ y, const double* __restrict__ U, float2* __restrict__ v,
-    double2* __restrict__ z, const double2* __restrict__ w, double mu, double lambda,
-    const double* __restrict__ part, const int32_t* __restrict__ bids,
-    const int32_t* __restrict__ boff, const double* __restrict__ eps) {
-  constexpr int R = T + 7;
-  __shared__ float acc[2 * R * R];
+__global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
+    float2* __restrict__ scratch, int Kx, int Ky, const Item* __restrict__ items, int n_items,
+    const Seg* __restrict__ segs, const float* __restrict__ wu, const float* __restrict__ wv,
+    const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
+    const float2* __restrict__ vin, const float2* __restrict__ y, const double* __restrict__ U,
+    float2* __restrict__ v, double2* __restrict__ z, const double2* __restrict__ w, double mu,
+    double lambda, const double* __restrict__ bfac, const int32_t* __restrict__ binside) {
+  constexpr int R = GridCfg<T>::R;
+  constexpr int NW = GridCfg<T>::NW;
+  __shared__ float2 acc[NW][R * R];
+  __shared__ float wts[NW][64][2 * KB_TAPS];
   __shared__ float coef[KB_TAPS * KB_NC];
-  __shared__ double s_fac;
-  __shared__ int s_inside;
-  const int ci = xcd_remap(blockIdx.x, gridDim.x);
-  if (ci >= n_chunks) return;
-  const Chunk ch = chunks[ci];
-  const int r0 = ch.ty * T, c0 = ch.tx * T;
-  for (int i = threadIdx.x; i < 2 * R * R; i += blockDim.x) acc[i] = 0.f;
+  const int ii = xcd_remap(blockIdx.x, gridDim.x);
+  if (ii >= n_items) return;
+  const Item it = items[ii];
+  const int r0 = it.ty * T, c0 = it.tx * T;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < NW * R * R; i += blockDim.x) (&acc[0][0])[i] = make_float2(0.f, 0.f);
   if (threadIdx.x < KB_TAPS * KB_NC) coef[threadIdx.x] = kbc[threadIdx.x];
-  if (DUAL && threadIdx.x < 64) {
-    const double r = sqrt(block_norm2(ch.block, part, bids, boff));
-    if (threadIdx.x == 0) {
-      const double e = eps[ch.block];
-      s_inside = r <= e;
-      s_fac = r > e ? e / r : 1.0;
-    }
-  }
   __syncthreads();
-  for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
-    const int pi = ch.start + k;
-    Taps t;
-    taps_for<T>(wu[pi], wv[pi], su, sv, Kx, Ky, c0, r0, coef, t);
-    float2 val;
-    if (!DUAL) {
-      val = vin[pi];
-    } else {
-      // last Algorithm 2 projection, then steps 10-11
-      const double2 we = w[pi], ze = z[pi];
-      const double Ue = U[pi];
-      const float2 ye = y[pi], vo = v[pi];
-      const double mU = mu * Ue;
-      double zx, zy;
-      project(ze.x - mU * (ze.x - we.x), ze.y - mU * (ze.y - we.y), ye, s_inside, s_fac, zx, zy);
-      z[pi] = make_double2(zx, zy);
-      const double vbx = Ue * (we.x - zx), vby = Ue * (we.y - zy);
-      const float2 vn = make_float2(float(double(vo.x) + lambda * (vbx - double(vo.x))),
-                                    float(double(vo.y) + lambda * (vby - double(vo.y))));
-      v[pi] = vn;
-      val = vn;
+  float2* myacc = acc[wid];
+  float* mywts = &wts[wid][0][0];
+  const int ta = lane >> 3, tb = lane & 7;   // tap of this lane in the apply phase
+  for (int s = it.seg0; s < it.seg1; ++s) {
+    const Seg sg = segs[s];
+    double fac = 1.0;
+    bool inside = true;
+    if (DUAL) {
+      fac = bfac[sg.block];
+      inside = binside[sg.block] != 0;
     }
-    const float th = theta ? theta[pi] : 1.0f;
-    val.x *= th;
-    val.y *= th;
+    const int q = (sg.count + NW - 1) / NW;
+    const int k0 = min(wid * q, sg.count), k1 = min(k0 + q, sg.count);
+    for (int base = k0; base < k1; base += 64) {
+      const int nb = min(64, k1 - base);
+      // prepare: one visibility per lane
+      int pos = 0;
+      float vx = 0.f, vy = 0.f;
+      if (lane < nb) {
+        const int pi = sg.start + base + lane;
+        Taps t;
+        taps_for<T>(wu[pi], wv[pi], su, sv, Kx, Ky, c0, r0, coef, t);
+        float2 val;
+        if (!DUAL) {
+          val = vin[pi];
+        } else {
+          // last Algorithm 2 projection z = P_B(q), then steps 10-11
+          const double2 we = w[pi], ze = z[pi];
+          const double Ue = U[pi];
+          const float2 ye = y[pi], vo = v[pi];
+          const double mU = mu * Ue;
+          const double qx = ze.x - mU * (ze.x - we.x), qy = ze.y - mU * (ze.y - we.y);
+          const double zx = inside ? qx : double(ye.x) + (qx - double(ye.x)) * fac;
+          const double zy = inside ? qy : double(ye.y) + (qy - double(ye.y)) * fac;
+          z[pi] = make_double2(zx, zy);
+          const double vbx = Ue * (we.x - zx), vby = Ue * (we.y - zy);
+          const float2 vn = make_float2(float(double(vo.x) + lambda * (vbx - double(vo.x))),
+                                        float(double(vo.y) + lambda * (vby - double(vo.y))));
+          v[pi] = vn;
+          val = vn;
+        }
+        const float th = theta ? theta[pi] : 1.0f;
+        vx = val.x * th;
+        vy = val.y * th;
+        pos = t.ov * R + t.ou;
+        float* wl = mywts + lane * (2 * KB_TAPS);
 #pragma unroll
-    for (int a = 0; a < KB_TAPS; ++a) {
-      const float ra = t.wy[a] * val.x, ia = t.wy[a] * val.y;
-      float* rowp = acc + 2 * ((t.ov + a) * R + t.ou);
-#pragma unroll
-      for (int b = 0; b < KB_TAPS; ++b) {
-        atomicAdd(rowp + 2 * b, t.wx[b] * ra);
-        atomicAdd(rowp + 2 * b + 1, t.wx[b] * ia);
+        for (int m = 0; m < KB_TAPS; ++m) {
+          wl[m] = t.wx[m];
+          wl[KB_TAPS + m] = t.wy[m];
+        }
       }
+      __builtin_amdgcn_wave_barrier();
+      // apply: the wave adds one visibility's 64 taps at a time, lane (a, b)
+      // owning tap (a, b), so the wave's 64 updates touch distinct cells
+      for (int k = 0; k < nb; ++k) {
+        const int pk = __builtin_amdgcn_readlane(pos, k);
+        const float ax = lane_f(vx, k), ay = lane_f(vy, k);
+        const float wgt = mywts[k * (2 * KB_TAPS) + tb] * mywts[k * (2 * KB_TAPS) + KB_TAPS + ta];
+        float2* cell = myacc + pk + ta * R + tb;
+        float2 c = *cell;
+        c.x = fmaf(wgt, ax, c.x);
+        c.y = fmaf(wgt, ay, c.y);
+        *cell = c;
+      }
+      __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();
+  float2* dst = scratch + size_t(ii) * (R * R);
   for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
-    const float re = acc[2 * i], im = acc[2 * i + 1];
-    if (re != 0.f || im != 0.f) {
-      const int a = i / R, b = i - a * R;
-      float* gp = reinterpret_cast<float*>(grid + size_t((r0 + a) & (Ky - 1)) * Kx + ((c0 + b) & (Kx - 1)));
-      atomicAdd(gp, re);
-      atomicAdd(gp + 1, im);
+    float sx = 0.f, sy = 0.f;
+#pragma unroll
+    for (int q2 = 0; q2 < NW; ++q2) {
+      sx += acc[q2][i].x;
+      sy += acc[q2][i].y;
     }
+    dst[i] = make_float2(sx, sy);
   }
 }
 
-template <int ELEM>
-struct Elem;
-template <> struct Elem<4> { using type = float; };
-template <> struct Elem<8> { using type = float2; };
-template <> struct Elem<16> { using type = double2; };
+// Sum the item partials into the grid: cell (a, b) of tile (tx, ty) gets the
+// region cell (a, b) of that tile's items, (a, T+b) of the left tile's items
+// when b < 7, (T+a, b) of the upper tile's when a < 7, and (T+a, T+b) of the
+// upper-left tile's when both are.  Every grid cell is written once.
+template <int T>
+__global__ __launch_bounds__(256) void k_fold(const float2* __restrict__ scratch,
+                                              const int32_t* __restrict__ tio, int tiles_x, int tiles_y,
+                                              int Kx, float2* __restrict__ grid) {
+  constexpr int R = T + 7;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  if (t >= tiles_x * tiles_y) return;
+  const int tx = t % tiles_x, ty = t / tiles_x;
+  const int lx = (tx + tiles_x - 1) % tiles_x, uy = (ty + tiles_y - 1) % tiles_y;
+  const int tl = ty * tiles_x + lx, tu = uy * tiles_x + tx, tul = uy * tiles_x + lx;
+  const int i0 = tio[t], i1 = tio[t + 1];
+  const int l0 = tio[tl], l1 = tio[tl + 1];
+  const int u0 = tio[tu], u1 = tio[tu + 1];
+  const int q0 = tio[tul], q1 = tio[tul + 1];
+  for (int c = threadIdx.x; c < T * T; c += blockDim.x) {
+    const int a = c / T, b = c - a * T;
+    float sx = 0.f, sy = 0.f;
+    for (int i = i0; i < i1; ++i) {
+      const float2 g = scratch[size_t(i) * (R * R) + a * R + b];
+      sx += g.x;
+      sy += g.y;
+    }
+    if (b < 7)
+      for (int i = l0; i < l1; ++i) {
+        const float2 g = scratch[size_t(i) * (R * R) + a * R + T + b];
+        sx += g.x;
+        sy += g.y;
+      }
+    if (a < 7) {
+      for (int i = u0; i < u1; ++i) {
+        const float2 g = scratch[size_t(i) * (R * R) + (T + a) * R + b];
+        sx += g.x;
+        sy += g.y;
+      }
+      if (b < 7)
+        for (int i = q0; i < q1; ++i) {
+          const float2 g = scratch[size_t(i) * (R * R) + (T + a) * R + T + b];
+          sx += g.x;
+          sy += g.y;
+        }
+    }
+    grid[size_t(ty * T + a) * Kx + (tx * T + b)] = make_float2(sx, sy);
+  }
+}
+
+// Projection factor of every block from its segment partials of
+// ||q - y_j||^2: inside (r <= eps_j) or scale eps_j / r.  One wave per block,
+// fixed summation order.
+__global__ void k_block_scale(const double* __restrict__ part, const int32_t* __restrict__ bids,
+                              const int32_t* __restrict__ boff, const double* __restrict__ eps, int d,
+                              double* __restrict__ bfac, int32_t* __restrict__ binside) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = wid; j < d; j += nw) {
+    double s = 0.0;
+    for (int c = boff[j] + lane; c < boff[j + 1]; c += 64) s += part[bids[c]];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) {
+      const double r = sqrt(s), e = eps[j];
+      binside[j] = r <= e;
+      bfac[j] = r > e ? e / r : 1.0;
+    }
+  }
+}
 
 template <typename E>
 __global__ void k_permute(const int32_t* __restrict__ perm, int64_t M, int to_user,
@@ -238,12 +324,12 @@ template <int T>
 int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double* part_out) {
   if (!dual) {
     hipLaunchKernelGGL((k_degrid<T, false>), dim3(p->n_launch), dim3(256), 0, p->stream, p->grid_f,
-                       p->Kx, p->Ky, p->chunks, p->n_chunks, p->wu, p->wv, p->theta, p->su_scale,
+                       p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, out, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0,
                        nullptr, nullptr);
   } else {
     hipLaunchKernelGGL((k_degrid<T, true>), dim3(p->n_launch), dim3(256), 0, p->stream, p->grid_f,
-                       p->Kx, p->Ky, p->chunks, p->n_chunks, p->wu, p->wv, p->theta, p->su_scale,
+                       p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->wbuf, a->mu,
                        part_out, p->rpart);
   }
@@ -252,18 +338,26 @@ int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double
 }
 
 template <int T>
-int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, const double* part_in) {
+int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a) {
   if (!dual) {
-    hipLaunchKernelGGL((k_grid<T, false>), dim3(p->n_launch), dim3(256), 0, p->stream, p->grid_a,
-                       p->Kx, p->Ky, p->chunks, p->n_chunks, p->wu, p->wv, p->theta, p->su_scale,
+    hipLaunchKernelGGL((k_grid<T, false>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
+                       p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, vin, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0,
-                       0.0, nullptr, nullptr, nullptr, nullptr);
+                       0.0, nullptr, nullptr);
   } else {
-    hipLaunchKernelGGL((k_grid<T, true>), dim3(p->n_launch), dim3(256), 0, p->stream, p->grid_a,
-                       p->Kx, p->Ky, p->chunks, p->n_chunks, p->wu, p->wv, p->theta, p->su_scale,
+    hipLaunchKernelGGL((k_grid<T, true>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
+                       p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->wbuf, a->mu,
-                       a->lambda, part_in, p->bchunk_ids, p->bchunk_off_d, p->eps_d);
+                       a->lambda, p->bfac, p->binside);
   }
+  PPD_HIP(hipGetLastError());
+  return PPD_OK;
+}
+
+template <int T>
+int launch_fold(ppd_plan* p) {
+  hipLaunchKernelGGL(k_fold<T>, dim3(p->n_tile_launch), dim3(256), 0, p->stream, p->gscratch,
+                     p->tile_item_off, p->tiles_x, p->tiles_y, p->Kx, p->grid_a);
   PPD_HIP(hipGetLastError());
   return PPD_OK;
 }
@@ -281,14 +375,14 @@ int dispatch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, doub
   return timer_end(p, slot);
 }
 
-int dispatch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, const double* part_in) {
+int dispatch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a) {
   int slot;
   PPD_TRY(timer_begin(p, KK_GRID, &slot));
   int st;
   switch (p->T) {
-    case 16: st = launch_grid<16>(p, dual, vin, a, part_in); break;
-    case 32: st = launch_grid<32>(p, dual, vin, a, part_in); break;
-    default: st = launch_grid<64>(p, dual, vin, a, part_in); break;
+    case 16: st = launch_grid<16>(p, dual, vin, a); break;
+    case 32: st = launch_grid<32>(p, dual, vin, a); break;
+    default: st = launch_grid<64>(p, dual, vin, a); break;
   }
   PPD_TRY(st);
   return timer_end(p, slot);
@@ -300,9 +394,38 @@ int degrid_plain(ppd_plan* p, float2* out) { return dispatch_degrid(p, false, ou
 int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out) {
   return dispatch_degrid(p, true, nullptr, &a, part_out);
 }
-int grid_plain(ppd_plan* p, const float2* v) { return dispatch_grid(p, false, v, nullptr, nullptr); }
+
+int grid_plain(ppd_plan* p, const float2* v) {
+  PPD_TRY(dispatch_grid(p, false, v, nullptr));
+  return fold_grid(p);
+}
+
 int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in) {
-  return dispatch_grid(p, true, nullptr, &a, part_in);
+  PPD_TRY(block_scale(p, part_in));
+  PPD_TRY(dispatch_grid(p, true, nullptr, &a));
+  return fold_grid(p);
+}
+
+int fold_grid(ppd_plan* p) {
+  int slot;
+  PPD_TRY(timer_begin(p, KK_FOLD, &slot));
+  int st;
+  switch (p->T) {
+    case 16: st = launch_fold<16>(p); break;
+    case 32: st = launch_fold<32>(p); break;
+    default: st = launch_fold<64>(p); break;
+  }
+  PPD_TRY(st);
+  return timer_end(p, slot);
+}
+
+int block_scale(ppd_plan* p, const double* part) {
+  int slot;
+  PPD_TRY(timer_begin(p, KK_NORM, &slot));
+  hipLaunchKernelGGL(k_block_scale, dim3(1), dim3(256), 0, p->stream, part, p->bseg_ids, p->bseg_off_d,
+                     p->eps_d, p->d, p->bfac, p->binside);
+  PPD_HIP(hipGetLastError());
+  return timer_end(p, slot);
 }
 
 int permute(ppd_plan* p, int direction, const void* in, void* out, int elem_bytes) {
@@ -349,7 +472,6 @@ extern "C" int ppd_phit(ppd_plan* p, const float* y, float* x, int order) {
     PPD_TRY(permute(p, PPD_USER_TO_PLAN, y, p->ybuf, 8));
     v = p->ybuf;
   }
-  PPD_TRY(zero_grid(p, p->grid_a));
   PPD_TRY(grid_plain(p, v));
   return fft_adjoint(p, x);
 }

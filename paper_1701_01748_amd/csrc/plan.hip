@@ -22,7 +22,7 @@ int fail(int status, const std::string& msg) {
 const char* kernel_kind_name(int k) {
   static const char* names[KK_COUNT] = {
       "fft_rows_fwd", "fft_cols_fwd", "degrid", "grid", "fft_cols_inv", "fft_rows_inv",
-      "zero", "permute", "subiter", "dwt", "idwt", "stats", "plain_dual", "hist", "norm", "misc"};
+      "fold", "permute", "subiter", "dwt", "idwt", "stats", "plain_dual", "hist", "norm", "misc"};
   return (k >= 0 && k < KK_COUNT) ? names[k] : "?";
 }
 
@@ -303,7 +303,9 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   }
   p->perm_host.resize(M);
   std::vector<int64_t> cnt(ntiles + 1);
-  std::vector<Chunk> chunks;
+  // bins (block j, tile t) -> plan range, collected per tile in block order
+  struct Bin { int64_t start, count; int32_t block; };
+  std::vector<std::vector<Bin>> tile_bins(ntiles);
   for (int j = 0; j < p->d; ++j) {
     const int64_t b0 = p->block_off[j], b1 = p->block_off[j + 1];
     std::fill(cnt.begin(), cnt.end(), 0);
@@ -311,38 +313,58 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
     for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
     std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
     for (int64_t i = b0; i < b1; ++i) p->perm_host[b0 + pos[key[i]]++] = int32_t(i);
-    for (int t = 0; t < ntiles; ++t) {
-      const int64_t n = cnt[t + 1] - cnt[t];
-      if (n == 0) continue;
-      const int64_t nch = (n + chunk_max - 1) / chunk_max;
-      for (int64_t c = 0; c < nch; ++c) {
-        const int64_t s = n * c / nch, e = n * (c + 1) / nch;
-        Chunk ch{};
-        ch.start = int32_t(b0 + cnt[t] + s);
-        ch.count = int32_t(e - s);
-        ch.tx = t % p->tiles_x;
-        ch.ty = t / p->tiles_x;
-        ch.block = j;
-        chunks.push_back(ch);
+    for (int t = 0; t < ntiles; ++t)
+      if (cnt[t + 1] > cnt[t]) tile_bins[t].push_back({b0 + cnt[t], cnt[t + 1] - cnt[t], j});
+  }
+  // work items: each tile's visibilities (all blocks) cut into <= chunk_max
+  // pieces of near-equal size; a piece is a list of per-block segments
+  std::vector<Item> items;
+  std::vector<Seg> segs;
+  std::vector<int32_t> tile_item_off(ntiles + 1, 0);
+  for (int t = 0; t < ntiles; ++t) {
+    int64_t total = 0;
+    for (const Bin& b : tile_bins[t]) total += b.count;
+    tile_item_off[t] = int32_t(items.size());
+    if (total == 0) continue;
+    const int64_t nit = (total + chunk_max - 1) / chunk_max;
+    size_t bi = 0;
+    int64_t used = 0;   // visibilities of tile_bins[t][bi] already assigned
+    for (int64_t k = 0; k < nit; ++k) {
+      int64_t want = total * (k + 1) / nit - total * k / nit;
+      Item it{};
+      it.tx = t % p->tiles_x;
+      it.ty = t / p->tiles_x;
+      it.seg0 = int32_t(segs.size());
+      while (want > 0) {
+        const Bin& b = tile_bins[t][bi];
+        const int64_t take = std::min(want, b.count - used);
+        segs.push_back({int32_t(b.start + used), int32_t(take), b.block, int32_t(items.size())});
+        used += take;
+        want -= take;
+        if (used == b.count) {
+          ++bi;
+          used = 0;
+        }
       }
+      it.seg1 = int32_t(segs.size());
+      items.push_back(it);
     }
   }
-  // launch order: spatial (tile row, tile column), then block
-  std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk& a, const Chunk& b) {
-    if (a.ty != b.ty) return a.ty < b.ty;
-    if (a.tx != b.tx) return a.tx < b.tx;
-    return a.block < b.block;
-  });
-  p->n_chunks = int(chunks.size());
-  p->n_launch = ((p->n_chunks + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
-  p->chunks_host = chunks;
-  p->bchunk_off.assign(p->d + 1, 0);
-  for (const Chunk& c : chunks) p->bchunk_off[c.block + 1]++;
-  for (int j = 0; j < p->d; ++j) p->bchunk_off[j + 1] += p->bchunk_off[j];
-  std::vector<int32_t> bids(p->n_chunks);
+  tile_item_off[ntiles] = int32_t(items.size());
+  p->n_items = int(items.size());
+  p->n_segs = int(segs.size());
+  p->n_tiles = ntiles;
+  p->n_launch = ((p->n_items + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
+  p->n_tile_launch = ((ntiles + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
+  p->items_host = items;
+  p->segs_host = segs;
+  p->bseg_off.assign(p->d + 1, 0);
+  for (const Seg& sg : segs) p->bseg_off[sg.block + 1]++;
+  for (int j = 0; j < p->d; ++j) p->bseg_off[j + 1] += p->bseg_off[j];
+  std::vector<int32_t> bids(p->n_segs);
   {
-    std::vector<int32_t> fill(p->bchunk_off.begin(), p->bchunk_off.end() - 1);
-    for (int c = 0; c < p->n_chunks; ++c) bids[fill[chunks[c].block]++] = c;
+    std::vector<int32_t> fill(p->bseg_off.begin(), p->bseg_off.end() - 1);
+    for (int c = 0; c < p->n_segs; ++c) bids[fill[segs[c].block]++] = c;
   }
 
   // ---- host tables -----------------------------------------------------------
@@ -392,9 +414,14 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   A(dalloc(p, &p->wv, M));
   if (D.theta) A(dalloc(p, &p->theta, M));
   A(dalloc(p, &p->perm, M));
-  A(dalloc(p, &p->chunks, p->n_chunks));
-  A(dalloc(p, &p->bchunk_ids, p->n_chunks));
-  A(dalloc(p, &p->bchunk_off_d, p->d + 1));
+  A(dalloc(p, &p->items, p->n_items));
+  A(dalloc(p, &p->segs, p->n_segs));
+  A(dalloc(p, &p->tile_item_off, ntiles + 1));
+  A(dalloc(p, &p->bseg_ids, p->n_segs));
+  A(dalloc(p, &p->bseg_off_d, p->d + 1));
+  A(dalloc(p, &p->gscratch, size_t(p->n_items) * (p->T + 7) * (p->T + 7)));
+  A(dalloc(p, &p->bfac, p->d));
+  A(dalloc(p, &p->binside, p->d));
   A(dalloc(p, &p->vis_block, M));
   A(dalloc(p, &p->kbc, KB_TAPS * KB_NC));
   A(dalloc(p, &p->dpx, p->nx));
@@ -408,8 +435,8 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   A(dalloc(p, &p->ybuf, M));
   A(dalloc(p, &p->wbuf, M));
   A(dalloc(p, &p->qbuf, M));
-  A(dalloc(p, &p->part, 2 * size_t(p->n_chunks)));
-  A(dalloc(p, &p->rpart, p->n_chunks));
+  A(dalloc(p, &p->part, 2 * size_t(p->n_segs)));
+  A(dalloc(p, &p->rpart, p->n_segs));
   A(dalloc(p, &p->eps_d, p->d));
   A(dalloc(p, &p->ppart, size_t(p->ny) * 4));
   A(dalloc(p, &p->stats_d, 8 + p->d));
@@ -439,9 +466,11 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   up(p->wv, wv.data(), 4 * M);
   if (D.theta) up(p->theta, th.data(), 4 * M);
   up(p->perm, p->perm_host.data(), 4 * M);
-  up(p->chunks, chunks.data(), sizeof(Chunk) * p->n_chunks);
-  up(p->bchunk_ids, bids.data(), 4 * p->n_chunks);
-  up(p->bchunk_off_d, p->bchunk_off.data(), 4 * (p->d + 1));
+  up(p->items, items.data(), sizeof(Item) * p->n_items);
+  up(p->segs, segs.data(), sizeof(Seg) * p->n_segs);
+  up(p->tile_item_off, tile_item_off.data(), 4 * (ntiles + 1));
+  up(p->bseg_ids, bids.data(), 4 * p->n_segs);
+  up(p->bseg_off_d, p->bseg_off.data(), 4 * (p->d + 1));
   up(p->vis_block, vblk.data(), 4 * M);
   up(p->kbc, kbc, sizeof(kbc));
   up(p->dpx, dpx.data(), 4 * p->nx);
@@ -449,8 +478,6 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   up(p->twx, twx.data(), sizeof(float2) * twx.size());
   up(p->twy, twy.data(), sizeof(float2) * twy.size());
   up(p->filt, filt.data(), 4 * filt.size());
-  if (st == PPD_OK && hipMemset(p->grid_a, 0, sizeof(float2) * K2) != hipSuccess)
-    st = fail(PPD_EDEVICE, "hipMemset failed");
   if (st == PPD_OK && hipDeviceSynchronize() != hipSuccess) st = fail(PPD_EDEVICE, "sync failed");
   if (st != PPD_OK) {
     destroy_plan(p);
@@ -491,7 +518,7 @@ int ppd_plan_get_info(const ppd_plan* p, ppd_plan_info* info) {
   info->levels = p->levels;
   info->tile = p->T;
   info->chunk = p->chunk_max;
-  info->n_chunks = p->n_chunks;
+  info->n_chunks = p->n_items;
   info->kb_beta = p->beta;
   info->device_bytes = p->device_bytes;
   return PPD_OK;

@@ -36,16 +36,22 @@ constexpr int N_BASES = 9;        // Dirac + db1..db8
 constexpr int FILT_STRIDE = 16;   // max Daubechies taps (db8)
 constexpr int MAX_XCD = 8;
 
-// One workgroup's work: visibilities [start, start+count) of plan order,
-// all in data block `block` with first tap in grid tile (tx, ty).
-struct Chunk {
-  int32_t start, count, tx, ty, block, pad0, pad1, pad2;
+// A segment: plan-order visibilities [start, start+count) of one data
+// block whose first tap lies in one grid tile.
+struct Seg {
+  int32_t start, count, block, item;
+};
+// A work item (one workgroup): the segments [seg0, seg1) of tile (tx, ty),
+// at most chunk_max visibilities.  Items are ordered tile by tile in
+// row-major tile order.
+struct Item {
+  int32_t tx, ty, seg0, seg1;
 };
 
 // Kernel kinds for the optional per-launch event timer.
 enum KernelKind {
   KK_FFT_ROWS_FWD, KK_FFT_COLS_FWD, KK_DEGRID, KK_GRID, KK_FFT_COLS_INV, KK_FFT_ROWS_INV,
-  KK_ZERO, KK_PERMUTE, KK_SUBITER, KK_DWT, KK_IDWT, KK_STATS, KK_PLAIN_DUAL, KK_HIST,
+  KK_FOLD, KK_PERMUTE, KK_SUBITER, KK_DWT, KK_IDWT, KK_STATS, KK_PLAIN_DUAL, KK_HIST,
   KK_NORM, KK_MISC, KK_COUNT
 };
 const char* kernel_kind_name(int k);
@@ -67,19 +73,26 @@ struct ppd_plan {
   // host copies
   std::vector<int64_t> block_off;          // [d+1]
   std::vector<int32_t> perm_host;          // plan -> user
-  std::vector<ppd::Chunk> chunks_host;     // launch order
-  std::vector<int32_t> bchunk_off;         // [d+1] into bchunk_ids
-  int n_chunks = 0;
-  int n_launch = 0;                        // chunk launches padded to XCD multiple
+  std::vector<ppd::Item> items_host;       // launch order
+  std::vector<ppd::Seg> segs_host;
+  std::vector<int32_t> bseg_off;           // [d+1] into bseg_ids
+  int n_items = 0, n_segs = 0;
+  int n_launch = 0;                        // item launches padded to an XCD multiple
+  int n_tiles = 0, n_tile_launch = 0;
 
   // device: coverage and plan tables
   float* wu = nullptr;
   float* wv = nullptr;
   float* theta = nullptr;
   int32_t* perm = nullptr;
-  ppd::Chunk* chunks = nullptr;
-  int32_t* bchunk_ids = nullptr;           // chunk ids grouped by block
-  int32_t* bchunk_off_d = nullptr;         // [d+1]
+  ppd::Item* items = nullptr;
+  ppd::Seg* segs = nullptr;
+  int32_t* tile_item_off = nullptr;        // [n_tiles+1] items of each tile
+  int32_t* bseg_ids = nullptr;             // segment ids grouped by block
+  int32_t* bseg_off_d = nullptr;           // [d+1]
+  float2* gscratch = nullptr;              // [n_items][(T+7)^2] gridding partials
+  double* bfac = nullptr;                  // [d] projection factor per block
+  int32_t* binside = nullptr;              // [d] 1 when the block is inside its ball
   int32_t* vis_block = nullptr;            // plan index -> block (plain form)
   float* kbc = nullptr;                    // [8][10] tap polynomials
   float* dpx = nullptr;                    // [nx] 1/phi_hat(n_c / Kx)
@@ -95,8 +108,8 @@ struct ppd_plan {
   float2* ybuf = nullptr;                  // [M] complex64 scratch
   double2* wbuf = nullptr;                 // [M] complex128 w (dual prologue)
   double2* qbuf = nullptr;                 // [M] complex128 (plain form)
-  double* part = nullptr;                  // [2][n_chunks] block-norm partials
-  double* rpart = nullptr;                 // [n_chunks] residual partials
+  double* part = nullptr;                  // [2][n_segs] block-norm partials
+  double* rpart = nullptr;                 // [n_segs] residual partials
   double* eps_d = nullptr;                 // [d]
   std::vector<double> eps_cache;
   double* ppart = nullptr;                 // [ny][4] primal statistics partials
@@ -144,7 +157,8 @@ struct PrimalArgs {
   double* part;                                                // [ny][4]
 };
 int fft_rows_inverse_primal(ppd_plan* p, const PrimalArgs& a);  // half -> primal update
-int zero_grid(ppd_plan* p, float2* g);
+int fold_grid(ppd_plan* p);                                    // gscratch -> grid_a
+int block_scale(ppd_plan* p, const double* part);              // part -> bfac, binside
 
 int degrid_plain(ppd_plan* p, float2* out);                    // grid_f -> out (plan order)
 struct DualArgs {

@@ -6,6 +6,7 @@ import synth
 from oracle import ppd as O
 from oracle import problem as oprob
 from oracle import prox as oprox
+from oracle import sara as osara
 
 from gpu_util import announce, assert_op_close, dev, host, rel_err, require_gpu
 
@@ -49,7 +50,11 @@ def test_iterations_match_oracle(form, n_itr):
         assert_op_close(host(st.xt), ost.xt, what=f"x tilde after {ost.it}")
         assert_op_close(host(st.v), ost.v[perm], what=f"v after {ost.it}")
         assert_op_close(host(st.z), ost.z[perm], what=f"z after {ost.it}")
-        assert_op_close(host(st.u), ost.u, what=f"u after {ost.it}")
+        # u is clipped to [-alpha, alpha]; its error is that of the clip
+        # argument u + Psi^H x~, whose scale is the coefficient magnitude
+        u_scale = np.abs(osara.analysis(ost.xt)).max()
+        du = np.abs(host(st.u) - ost.u).max()
+        assert du <= 1e-5 * u_scale, f"u after {ost.it}: {du:.3e} vs scale {u_scale:.3e}"
 
 
 def test_first_iteration_closed_form_gpu():
