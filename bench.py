@@ -27,6 +27,44 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PPD iters/s + Phi/Phi^T vis/s at 512^2, M=1.3M; batched vs plain, HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+# kernel kind -> source file that defines it (traffic figures are only used
+# while that file is unchanged since the counters were taken)
+KIND_SOURCE = {"degrid": "nufft.hip", "grid": "nufft.hip", "fold": "nufft.hip",
+               "fft_rows_fwd": "fft.hip", "fft_cols_fwd": "fft.hip", "fft_cols_inv": "fft.hip",
+               "fft_rows_inv": "fft.hip", "dwt": "sara.hip", "idwt": "sara.hip", "subiter": "dual.hip"}
+
+
+def source_sha(name: str) -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1701_01748_amd", "csrc", name), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def measured_traffic(kind: str, workload: str, tile: int, chunk: int):
+    """HBM bytes per launch of `kind` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel factors),
+    or None if absent or taken on a different kernel source / configuration."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    src = KIND_SOURCE.get(kind)
+    if not src or vals.get(f"sha.{src}") != source_sha(src):
+        return None
+    if vals.get("tile") != str(tile) or vals.get("chunk") != str(chunk):
+        return None
+    try:
+        fetch = float(vals[f"{kind}.fetch_kib"]) * float(vals["fetch_factor"])
+        write = float(vals[f"{kind}.write_kib"]) * float(vals["write_factor"])
+    except KeyError:
+        return None
+    return (fetch + write) * 1024.0
 
 
 def algorithmic_bytes(kind: str, M: int, N: int, K: int, ny: int, Kx: int) -> float:
@@ -60,6 +98,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements (profiling runs)")
+    ap.add_argument("--tile", type=int, default=0, help="gridding tile edge (0: library default)")
+    ap.add_argument("--chunk", type=int, default=0, help="visibilities per work item (0: library default)")
+    ap.add_argument("--autotune", action="store_true", help="pick tile / chunk by timing candidates first")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 256 MiB device copy from an L2/MALL-evicted source (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -76,6 +119,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        nbytes = 256 << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        sweep = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        sweep.fill_(2.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": nbytes, "bytes_written": nbytes}))
+        return
     w = synth.WORKLOADS[args.workload]
     inp = synth.make_inputs(w)
     n = w.n
@@ -83,7 +137,11 @@ def main():
     M, N = w.M, n * n
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    plan = P.Plan(n, n, wu, wv, off, stream=stream)
+    tuned = None
+    if args.autotune:
+        from paper_1701_01748_amd import tune
+        (args.tile, args.chunk), tuned = tune.autotune(n, n, wu, wv, off, stream)
+    plan = P.Plan(n, n, wu, wv, off, stream=stream, tile=args.tile, chunk=args.chunk)
     info = plan.info
     K, Kx = info.Kx * info.Ky, info.Kx
     perm = plan.permutation()
@@ -146,9 +204,13 @@ def main():
     algo = algorithmic_bytes(dom, M, N, K, n, Kx)
     achieved = algo / avg_s / 1e9
     out["kernels"] = per_kind
+    traffic = measured_traffic(dom, args.workload, info.tile, info.chunk)
     out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": None if traffic is None else round(traffic),
                        "algorithmic_bytes_per_launch": algo, "avg_launch_us": round(avg_s * 1e6, 3)}
+    if tuned:
+        out["autotune_us_per_iteration"] = {f"tile{t}_chunk{c}": round(v, 1) for (t, c), v in tuned.items()}
 
     if not args.quick:
         # ---- Phi / Phi^H visibilities per second (plan order) ------------------------

@@ -68,8 +68,8 @@ typedef struct {
                                  pi sqrt(35.2) (width 8, 2x oversampling)        */
   int32_t levels;             /* SARA decomposition levels (1..6), 0 -> 3       */
   int32_t tile;               /* gridding tile edge in grid cells: 16, 32 or 64;
-                                 0 -> 32                                         */
-  int32_t chunk;              /* max visibilities per work chunk, 0 -> 1024     */
+                                 0 -> 16                                         */
+  int32_t chunk;              /* max visibilities per work chunk, 0 -> 512      */
 } ppd_plan_desc;
 
 /* Create a plan: validates desc, bins the visibilities by (block, tile) on

@@ -27,9 +27,12 @@ __device__ inline double block_sum(double v, double* red) {
 __global__ __launch_bounds__(256) void k_alg2(
     int mode, const Item* __restrict__ items, int n_items, const Seg* __restrict__ segs,
     const double2* __restrict__ w, const float2* __restrict__ y, const double* __restrict__ U,
-    double2* __restrict__ z, double mu, const double* __restrict__ bfac,
-    const int32_t* __restrict__ binside, double* __restrict__ part_out) {
+    double2* __restrict__ z, double mu, const double* __restrict__ part_in,
+    const int32_t* __restrict__ bids, const int32_t* __restrict__ boff, const double* __restrict__ eps,
+    double* __restrict__ part_out) {
   __shared__ double red[16];
+  __shared__ double s_fac;
+  __shared__ int s_inside;
   const int ii = xcd_remap(blockIdx.x, gridDim.x);
   if (ii >= n_items) return;
   const Item it = items[ii];
@@ -38,8 +41,11 @@ __global__ __launch_bounds__(256) void k_alg2(
     double fac = 1.0;
     bool inside = true;
     if (mode != 0) {
-      fac = bfac[sg.block];
-      inside = binside[sg.block] != 0;
+      if (threadIdx.x < 64) block_factor(sg.block, part_in, bids, boff, eps, &s_fac, &s_inside);
+      __syncthreads();
+      fac = s_fac;
+      inside = s_inside != 0;
+      __syncthreads();
     }
     double qn = 0.0;
     for (int k = threadIdx.x; k < sg.count; k += blockDim.x) {
@@ -195,11 +201,10 @@ int grid_blocks(int64_t n) { return int(std::min<int64_t>((n + PL_THREADS - 1) /
 
 int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* y, const double* U, double2* z,
                 double mu, const double* part_in, double* part_out) {
-  if (mode != 0) PPD_TRY(block_scale(p, part_in));
   int slot;
   PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
   hipLaunchKernelGGL(k_alg2, dim3(p->n_launch), dim3(256), 0, p->stream, mode, p->items, p->n_items,
-                     p->segs, w, y, U, z, mu, p->bfac, p->binside, part_out);
+                     p->segs, w, y, U, z, mu, part_in, p->bseg_ids, p->bseg_off_d, p->eps_d, part_out);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_degrid(
     const int a = i / R, b = i - a * R;
     reg[i] = grid[size_t((r0 + a) & (Ky - 1)) * Kx + ((c0 + b) & (Kx - 1))];
   }
-  if (threadIdx.x < KB_TAPS * KB_NC) coef[threadIdx.x] = kbc[threadIdx.x];
+  for (int i = threadIdx.x; i < KB_TAPS * KB_NC; i += blockDim.x) coef[i] = kbc[i];
   __syncthreads();
   for (int s = it.seg0; s < it.seg1; ++s) {
     const Seg sg = segs[s];
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_degrid(
       Taps t;
       taps_for<T>(wu[pi], wv[pi], su, sv, Kx, Ky, c0, r0, coef, t);
       float ax = 0.f, ay = 0.f;
-#pragma unroll
+#pragma unroll 2
       for (int a = 0; a < KB_TAPS; ++a) {
         const float2* row = reg + (t.ov + a) * R + t.ou;
         float sx = 0.f, sy = 0.f;
@@ -93,8 +93,10 @@ __global__ __launch_bounds__(256) void k_degrid(
           sx = fmaf(t.wx[b], g.x, sx);
           sy = fmaf(t.wx[b], g.y, sy);
         }
-        ax = fmaf(t.wy[a], sx, ax);
-        ay = fmaf(t.wy[a], sy, ay);
+        const float wya = a == 0 ? t.wy[0] : a == 1 ? t.wy[1] : a == 2 ? t.wy[2] : a == 3 ? t.wy[3]
+                        : a == 4 ? t.wy[4] : a == 5 ? t.wy[5] : a == 6 ? t.wy[6] : t.wy[7];
+        ax = fmaf(wya, sx, ax);
+        ay = fmaf(wya, sy, ay);
       }
       const float th = theta ? theta[pi] : 1.0f;
       const float2 g = make_float2(ax * th, ay * th);
@@ -128,18 +130,16 @@ __global__ __launch_bounds__(256) void k_degrid(
   }
 }
 
-// Waves per gridding workgroup: each wave owns a private copy of the
-// (T+7)^2 region in LDS.
+// Gridding workgroup shape: NW waves, each owning two private copies (A, B)
+// of the (T+7)^2 region in LDS.  Even visibilities of a batch go to copy A,
+// odd ones to copy B: two independent read-modify-write chains per wave
+// that the compiler may interleave (distinct LDS arrays cannot alias).
 template <int T>
 struct GridCfg {
   static constexpr int R = T + 7;
-  static constexpr int NW = (T >= 64) ? 2 : 4;
+  static constexpr int NW = (T <= 16) ? 4 : (T <= 32 ? 2 : 1);
   static constexpr int THREADS = NW * 64;
 };
-
-__device__ __forceinline__ float lane_f(float v, int k) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-}
 
 template <int T, bool DUAL>
 __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
@@ -148,41 +148,55 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
     const float2* __restrict__ vin, const float2* __restrict__ y, const double* __restrict__ U,
     float2* __restrict__ v, double2* __restrict__ z, const double2* __restrict__ w, double mu,
-    double lambda, const double* __restrict__ bfac, const int32_t* __restrict__ binside) {
+    double lambda, const double* __restrict__ part, const int32_t* __restrict__ bids,
+    const int32_t* __restrict__ boff, const double* __restrict__ eps) {
   constexpr int R = GridCfg<T>::R;
   constexpr int NW = GridCfg<T>::NW;
-  __shared__ float2 acc[NW][R * R];
-  __shared__ float wts[NW][64][2 * KB_TAPS];
+  __shared__ float2 acc_a[NW][R * R];
+  __shared__ float2 acc_b[NW][R * R];
+  __shared__ float2 wxv[NW][64 * KB_TAPS];   // wx[b] * value, per visibility of the batch
+  __shared__ float wyb[NW][64 * KB_TAPS];    // wy[a]
   __shared__ float coef[KB_TAPS * KB_NC];
+  __shared__ double s_fac;
+  __shared__ int s_inside;
   const int ii = xcd_remap(blockIdx.x, gridDim.x);
   if (ii >= n_items) return;
   const Item it = items[ii];
   const int r0 = it.ty * T, c0 = it.tx * T;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < NW * R * R; i += blockDim.x) (&acc[0][0])[i] = make_float2(0.f, 0.f);
-  if (threadIdx.x < KB_TAPS * KB_NC) coef[threadIdx.x] = kbc[threadIdx.x];
+  for (int i = threadIdx.x; i < NW * R * R; i += blockDim.x) {
+    (&acc_a[0][0])[i] = make_float2(0.f, 0.f);
+    (&acc_b[0][0])[i] = make_float2(0.f, 0.f);
+  }
+  for (int i = threadIdx.x; i < KB_TAPS * KB_NC; i += blockDim.x) coef[i] = kbc[i];
   __syncthreads();
-  float2* myacc = acc[wid];
-  float* mywts = &wts[wid][0][0];
+  float2* accA = acc_a[wid];
+  float2* accB = acc_b[wid];
+  float2* mywxv = wxv[wid];
+  float* mywy = wyb[wid];
   const int ta = lane >> 3, tb = lane & 7;   // tap of this lane in the apply phase
+  const int lofs = ta * R + tb;
   for (int s = it.seg0; s < it.seg1; ++s) {
     const Seg sg = segs[s];
     double fac = 1.0;
     bool inside = true;
     if (DUAL) {
-      fac = bfac[sg.block];
-      inside = binside[sg.block] != 0;
+      if (threadIdx.x < 64) block_factor(sg.block, part, bids, boff, eps, &s_fac, &s_inside);
+      __syncthreads();
+      fac = s_fac;
+      inside = s_inside != 0;
+      __syncthreads();
     }
     const int q = (sg.count + NW - 1) / NW;
     const int k0 = min(wid * q, sg.count), k1 = min(k0 + q, sg.count);
     for (int base = k0; base < k1; base += 64) {
       const int nb = min(64, k1 - base);
-      // prepare: one visibility per lane
+      // prepare: one visibility per lane (lanes past nb carry zero weight)
       int pos = 0;
       float vx = 0.f, vy = 0.f;
+      Taps t;
       if (lane < nb) {
         const int pi = sg.start + base + lane;
-        Taps t;
         taps_for<T>(wu[pi], wv[pi], su, sv, Kx, Ky, c0, r0, coef, t);
         float2 val;
         if (!DUAL) {
@@ -207,25 +221,36 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
         vx = val.x * th;
         vy = val.y * th;
         pos = t.ov * R + t.ou;
-        float* wl = mywts + lane * (2 * KB_TAPS);
+      } else {
 #pragma unroll
         for (int m = 0; m < KB_TAPS; ++m) {
-          wl[m] = t.wx[m];
-          wl[KB_TAPS + m] = t.wy[m];
+          t.wx[m] = 0.f;
+          t.wy[m] = 0.f;
         }
       }
+#pragma unroll
+      for (int m = 0; m < KB_TAPS; ++m) {
+        mywxv[lane * KB_TAPS + m] = make_float2(t.wx[m] * vx, t.wx[m] * vy);
+        mywy[lane * KB_TAPS + m] = t.wy[m];
+      }
       __builtin_amdgcn_wave_barrier();
-      // apply: the wave adds one visibility's 64 taps at a time, lane (a, b)
-      // owning tap (a, b), so the wave's 64 updates touch distinct cells
-      for (int k = 0; k < nb; ++k) {
-        const int pk = __builtin_amdgcn_readlane(pos, k);
-        const float ax = lane_f(vx, k), ay = lane_f(vy, k);
-        const float wgt = mywts[k * (2 * KB_TAPS) + tb] * mywts[k * (2 * KB_TAPS) + KB_TAPS + ta];
-        float2* cell = myacc + pk + ta * R + tb;
-        float2 c = *cell;
-        c.x = fmaf(wgt, ax, c.x);
-        c.y = fmaf(wgt, ay, c.y);
-        *cell = c;
+      // apply: lane (a, b) owns tap (a, b) of one visibility at a time, so
+      // the wave's 64 read-modify-writes touch distinct cells (LDS float
+      // atomics are far slower on this part, collisions or not)
+      const int nb2 = (nb + 1) & ~1;
+      for (int k = 0; k < nb2; k += 2) {
+        const int pa = __builtin_amdgcn_readlane(pos, k) + lofs;
+        const int pb = __builtin_amdgcn_readlane(pos, k + 1) + lofs;
+        const float2 xa = mywxv[k * KB_TAPS + tb], xb = mywxv[(k + 1) * KB_TAPS + tb];
+        const float ga = mywy[k * KB_TAPS + ta], gb = mywy[(k + 1) * KB_TAPS + ta];
+        float2 ca = accA[pa];
+        float2 cb = accB[pb];
+        ca.x = fmaf(ga, xa.x, ca.x);
+        ca.y = fmaf(ga, xa.y, ca.y);
+        cb.x = fmaf(gb, xb.x, cb.x);
+        cb.y = fmaf(gb, xb.y, cb.y);
+        accA[pa] = ca;
+        accB[pb] = cb;
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -236,79 +261,58 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     float sx = 0.f, sy = 0.f;
 #pragma unroll
     for (int q2 = 0; q2 < NW; ++q2) {
-      sx += acc[q2][i].x;
-      sy += acc[q2][i].y;
+      sx += acc_a[q2][i].x + acc_b[q2][i].x;
+      sy += acc_a[q2][i].y + acc_b[q2][i].y;
     }
     dst[i] = make_float2(sx, sy);
   }
 }
 
-// Sum the item partials into the grid: cell (a, b) of tile (tx, ty) gets the
-// region cell (a, b) of that tile's items, (a, T+b) of the left tile's items
-// when b < 7, (T+a, b) of the upper tile's when a < 7, and (T+a, T+b) of the
-// upper-left tile's when both are.  Every grid cell is written once.
-template <int T>
-__global__ __launch_bounds__(256) void k_fold(const float2* __restrict__ scratch,
-                                              const int32_t* __restrict__ tio, int tiles_x, int tiles_y,
-                                              int Kx, float2* __restrict__ grid) {
-  constexpr int R = T + 7;
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  if (t >= tiles_x * tiles_y) return;
-  const int tx = t % tiles_x, ty = t / tiles_x;
-  const int lx = (tx + tiles_x - 1) % tiles_x, uy = (ty + tiles_y - 1) % tiles_y;
-  const int tl = ty * tiles_x + lx, tu = uy * tiles_x + tx, tul = uy * tiles_x + lx;
-  const int i0 = tio[t], i1 = tio[t + 1];
-  const int l0 = tio[tl], l1 = tio[tl + 1];
-  const int u0 = tio[tu], u1 = tio[tu + 1];
-  const int q0 = tio[tul], q1 = tio[tul + 1];
-  for (int c = threadIdx.x; c < T * T; c += blockDim.x) {
-    const int a = c / T, b = c - a * T;
-    float sx = 0.f, sy = 0.f;
-    for (int i = i0; i < i1; ++i) {
-      const float2 g = scratch[size_t(i) * (R * R) + a * R + b];
-      sx += g.x;
-      sy += g.y;
-    }
-    if (b < 7)
-      for (int i = l0; i < l1; ++i) {
-        const float2 g = scratch[size_t(i) * (R * R) + a * R + T + b];
-        sx += g.x;
-        sy += g.y;
-      }
-    if (a < 7) {
-      for (int i = u0; i < u1; ++i) {
-        const float2 g = scratch[size_t(i) * (R * R) + (T + a) * R + b];
-        sx += g.x;
-        sy += g.y;
-      }
-      if (b < 7)
-        for (int i = q0; i < q1; ++i) {
-          const float2 g = scratch[size_t(i) * (R * R) + (T + a) * R + T + b];
-          sx += g.x;
-          sy += g.y;
-        }
-    }
-    grid[size_t(ty * T + a) * Kx + (tx * T + b)] = make_float2(sx, sy);
+// One thread per grid cell (FOLD_CELLS cells per workgroup, T*T/FOLD_CELLS
+// workgroups per tile); the item loops are unrolled so their independent
+// loads overlap.
+constexpr int FOLD_CELLS = 256;
+
+__device__ __forceinline__ void fold_items(const float2* __restrict__ scratch, int R2, int off, int i0,
+                                           int i1, float& sx, float& sy) {
+  int i = i0;
+  for (; i + 4 <= i1; i += 4) {
+    const float2 g0 = scratch[size_t(i) * R2 + off];
+    const float2 g1 = scratch[size_t(i + 1) * R2 + off];
+    const float2 g2 = scratch[size_t(i + 2) * R2 + off];
+    const float2 g3 = scratch[size_t(i + 3) * R2 + off];
+    sx += (g0.x + g1.x) + (g2.x + g3.x);
+    sy += (g0.y + g1.y) + (g2.y + g3.y);
+  }
+  for (; i < i1; ++i) {
+    const float2 g = scratch[size_t(i) * R2 + off];
+    sx += g.x;
+    sy += g.y;
   }
 }
 
-// Projection factor of every block from its segment partials of
-// ||q - y_j||^2: inside (r <= eps_j) or scale eps_j / r.  One wave per block,
-// fixed summation order.
-__global__ void k_block_scale(const double* __restrict__ part, const int32_t* __restrict__ bids,
-                              const int32_t* __restrict__ boff, const double* __restrict__ eps, int d,
-                              double* __restrict__ bfac, int32_t* __restrict__ binside) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int j = wid; j < d; j += nw) {
-    double s = 0.0;
-    for (int c = boff[j] + lane; c < boff[j + 1]; c += 64) s += part[bids[c]];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) {
-      const double r = sqrt(s), e = eps[j];
-      binside[j] = r <= e;
-      bfac[j] = r > e ? e / r : 1.0;
-    }
+template <int T>
+__global__ __launch_bounds__(FOLD_CELLS) void k_fold(const float2* __restrict__ scratch,
+                                                     const int32_t* __restrict__ tio, int tiles_x,
+                                                     int tiles_y, int Kx, float2* __restrict__ grid) {
+  constexpr int R = T + 7;
+  constexpr int PARTS = (T * T) / FOLD_CELLS;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  if (wg >= tiles_x * tiles_y * PARTS) return;
+  const int t = wg / PARTS, part = wg - t * PARTS;
+  const int tx = t % tiles_x, ty = t / tiles_x;
+  const int lx = (tx + tiles_x - 1) % tiles_x, uy = (ty + tiles_y - 1) % tiles_y;
+  const int tl = ty * tiles_x + lx, tu = uy * tiles_x + tx, tul = uy * tiles_x + lx;
+  const int c = part * FOLD_CELLS + threadIdx.x;
+  const int a = c / T, b = c - a * T;
+  float sx = 0.f, sy = 0.f;
+  fold_items(scratch, R * R, a * R + b, tio[t], tio[t + 1], sx, sy);
+  if (b < 7) fold_items(scratch, R * R, a * R + T + b, tio[tl], tio[tl + 1], sx, sy);
+  if (a < 7) {
+    fold_items(scratch, R * R, (T + a) * R + b, tio[tu], tio[tu + 1], sx, sy);
+    if (b < 7) fold_items(scratch, R * R, (T + a) * R + T + b, tio[tul], tio[tul + 1], sx, sy);
   }
+  grid[size_t(ty * T + a) * Kx + (tx * T + b)] = make_float2(sx, sy);
 }
 
 template <typename E>
@@ -338,17 +342,17 @@ int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double
 }
 
 template <int T>
-int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a) {
+int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, const double* part_in) {
   if (!dual) {
     hipLaunchKernelGGL((k_grid<T, false>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, vin, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0,
-                       0.0, nullptr, nullptr);
+                       0.0, nullptr, nullptr, nullptr, nullptr);
   } else {
     hipLaunchKernelGGL((k_grid<T, true>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->wbuf, a->mu,
-                       a->lambda, p->bfac, p->binside);
+                       a->lambda, part_in, p->bseg_ids, p->bseg_off_d, p->eps_d);
   }
   PPD_HIP(hipGetLastError());
   return PPD_OK;
@@ -356,7 +360,9 @@ int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a) {
 
 template <int T>
 int launch_fold(ppd_plan* p) {
-  hipLaunchKernelGGL(k_fold<T>, dim3(p->n_tile_launch), dim3(256), 0, p->stream, p->gscratch,
+  const int n = p->n_tiles * ((T * T) / FOLD_CELLS);
+  const int nl = ((n + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
+  hipLaunchKernelGGL(k_fold<T>, dim3(nl), dim3(FOLD_CELLS), 0, p->stream, p->gscratch,
                      p->tile_item_off, p->tiles_x, p->tiles_y, p->Kx, p->grid_a);
   PPD_HIP(hipGetLastError());
   return PPD_OK;
@@ -375,14 +381,14 @@ int dispatch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, doub
   return timer_end(p, slot);
 }
 
-int dispatch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a) {
+int dispatch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, const double* part_in) {
   int slot;
   PPD_TRY(timer_begin(p, KK_GRID, &slot));
   int st;
   switch (p->T) {
-    case 16: st = launch_grid<16>(p, dual, vin, a); break;
-    case 32: st = launch_grid<32>(p, dual, vin, a); break;
-    default: st = launch_grid<64>(p, dual, vin, a); break;
+    case 16: st = launch_grid<16>(p, dual, vin, a, part_in); break;
+    case 32: st = launch_grid<32>(p, dual, vin, a, part_in); break;
+    default: st = launch_grid<64>(p, dual, vin, a, part_in); break;
   }
   PPD_TRY(st);
   return timer_end(p, slot);
@@ -396,13 +402,12 @@ int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out) {
 }
 
 int grid_plain(ppd_plan* p, const float2* v) {
-  PPD_TRY(dispatch_grid(p, false, v, nullptr));
+  PPD_TRY(dispatch_grid(p, false, v, nullptr, nullptr));
   return fold_grid(p);
 }
 
 int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in) {
-  PPD_TRY(block_scale(p, part_in));
-  PPD_TRY(dispatch_grid(p, true, nullptr, &a));
+  PPD_TRY(dispatch_grid(p, true, nullptr, &a, part_in));
   return fold_grid(p);
 }
 
@@ -416,15 +421,6 @@ int fold_grid(ppd_plan* p) {
     default: st = launch_fold<64>(p); break;
   }
   PPD_TRY(st);
-  return timer_end(p, slot);
-}
-
-int block_scale(ppd_plan* p, const double* part) {
-  int slot;
-  PPD_TRY(timer_begin(p, KK_NORM, &slot));
-  hipLaunchKernelGGL(k_block_scale, dim3(1), dim3(256), 0, p->stream, part, p->bseg_ids, p->bseg_off_d,
-                     p->eps_d, p->d, p->bfac, p->binside);
-  PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }
 

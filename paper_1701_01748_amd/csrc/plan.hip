@@ -255,9 +255,9 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
     if (D.block_off[j + 1] <= D.block_off[j])
       return fail(PPD_EINVAL, "block_off must be strictly increasing (no empty block)");
   if (!D.omega_u || !D.omega_v) return fail(PPD_EINVAL, "omega_u / omega_v required");
-  int T = D.tile == 0 ? 32 : D.tile;
+  int T = D.tile == 0 ? 16 : D.tile;
   if (T != 16 && T != 32 && T != 64) return fail(PPD_EINVAL, "tile must be 16, 32 or 64");
-  const int chunk_max = D.chunk == 0 ? 1024 : D.chunk;
+  const int chunk_max = D.chunk == 0 ? 512 : D.chunk;
   if (chunk_max < 64 || chunk_max > 65536) return fail(PPD_EINVAL, "chunk must be in [64, 65536]");
   const float lim = 3.14159274f;   // float32(pi) rounds above pi
   for (int64_t i = 0; i < D.M; ++i) {
@@ -293,13 +293,14 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   // ---- binning: counting sort by tile inside every block -------------------
   const int64_t M = D.M;
   const int ntiles = p->tiles_x * p->tiles_y;
-  std::vector<int32_t> key(M);
+  std::vector<int32_t> key(M), cell(M);
   for (int64_t i = 0; i < M; ++i) {
     const double tu = double(D.omega_u[i]) * p->su_scale;
     const double tv = double(D.omega_v[i]) * p->sv_scale;
     const int cu0 = (int(std::floor(tu)) - 3) & (p->Kx - 1);
     const int cv0 = (int(std::floor(tv)) - 3) & (p->Ky - 1);
     key[i] = (cv0 / p->T) * p->tiles_x + (cu0 / p->T);
+    cell[i] = cv0 * p->Kx + cu0;
   }
   p->perm_host.resize(M);
   std::vector<int64_t> cnt(ntiles + 1);
@@ -313,6 +314,13 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
     for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
     std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
     for (int64_t i = b0; i < b1; ++i) p->perm_host[b0 + pos[key[i]]++] = int32_t(i);
+    // inside each bin, order by first-tap cell (row-major within the tile):
+    // neighbouring lanes then touch neighbouring cells
+    for (int t = 0; t < ntiles; ++t) {
+      int32_t* a = p->perm_host.data() + b0 + cnt[t];
+      std::stable_sort(a, a + (cnt[t + 1] - cnt[t]),
+                       [&](int32_t x, int32_t y) { return cell[x] < cell[y]; });
+    }
     for (int t = 0; t < ntiles; ++t)
       if (cnt[t + 1] > cnt[t]) tile_bins[t].push_back({b0 + cnt[t], cnt[t + 1] - cnt[t], j});
   }
@@ -420,8 +428,6 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   A(dalloc(p, &p->bseg_ids, p->n_segs));
   A(dalloc(p, &p->bseg_off_d, p->d + 1));
   A(dalloc(p, &p->gscratch, size_t(p->n_items) * (p->T + 7) * (p->T + 7)));
-  A(dalloc(p, &p->bfac, p->d));
-  A(dalloc(p, &p->binside, p->d));
   A(dalloc(p, &p->vis_block, M));
   A(dalloc(p, &p->kbc, KB_TAPS * KB_NC));
   A(dalloc(p, &p->dpx, p->nx));

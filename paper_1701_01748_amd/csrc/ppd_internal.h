@@ -91,8 +91,6 @@ struct ppd_plan {
   int32_t* bseg_ids = nullptr;             // segment ids grouped by block
   int32_t* bseg_off_d = nullptr;           // [d+1]
   float2* gscratch = nullptr;              // [n_items][(T+7)^2] gridding partials
-  double* bfac = nullptr;                  // [d] projection factor per block
-  int32_t* binside = nullptr;              // [d] 1 when the block is inside its ball
   int32_t* vis_block = nullptr;            // plan index -> block (plain form)
   float* kbc = nullptr;                    // [8][10] tap polynomials
   float* dpx = nullptr;                    // [nx] 1/phi_hat(n_c / Kx)
@@ -158,7 +156,6 @@ struct PrimalArgs {
 };
 int fft_rows_inverse_primal(ppd_plan* p, const PrimalArgs& a);  // half -> primal update
 int fold_grid(ppd_plan* p);                                    // gscratch -> grid_a
-int block_scale(ppd_plan* p, const double* part);              // part -> bfac, binside
 
 int degrid_plain(ppd_plan* p, float2* out);                    // grid_f -> out (plan order)
 struct DualArgs {
@@ -198,6 +195,24 @@ __host__ __device__ inline void kb_weights(float s, const float* __restrict__ c,
 #pragma unroll
     for (int k = KB_DEG - 1; k >= 0; --k) acc = fmaf(acc, x, c[m * KB_NC + k]);
     w[m] = acc;
+  }
+}
+
+// Projection factor of data block j for P_B (Sec. 3.3, eq. proj-L2) from
+// the segment partials of ||q - y_j||^2: inside (r <= eps_j) or eps_j / r.
+// Called by one full wave; fixed summation order, so every workgroup gets
+// the same value.
+__device__ inline void block_factor(int j, const double* __restrict__ part, const int32_t* __restrict__ bids,
+                                    const int32_t* __restrict__ boff, const double* __restrict__ eps,
+                                    double* fac, int* inside) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int c = boff[j] + lane; c < boff[j + 1]; c += 64) s += part[bids[c]];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) {
+    const double r = sqrt(s), e = eps[j];
+    *inside = r <= e;
+    *fac = r > e ? e / r : 1.0;
   }
 }
 

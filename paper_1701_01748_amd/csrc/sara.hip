@@ -17,7 +17,8 @@ namespace ppd {
 namespace {
 
 constexpr int AT = 16;   // analysis output tile per sub-band
-constexpr int ST = 32;   // synthesis output tile
+constexpr int ST = 32;   // synthesis output tile (inner levels)
+constexpr int STF = 16;  // synthesis output tile of the last level (8 bases summed)
 constexpr int MAXR = 2 * AT + 2 * FILT_STRIDE;   // staged input extent
 
 struct SaraGeom {
@@ -226,10 +227,10 @@ __global__ __launch_bounds__(256) void k_idwt_final(const float* __restrict__ u,
   __shared__ float s_ll[SK * SK], s_lh[SK * SK], s_hl[SK * SK], s_hh[SK * SK];
   __shared__ float s_a[SK * ST], s_d[SK * ST];
   const int hh = g.ny, ww = g.nx;
-  const int tsy = min(ST, hh), tsx = min(ST, ww);
+  const int tsy = min(STF, hh), tsx = min(STF, ww);
   const int y0 = blockIdx.y * tsy, x0 = blockIdx.x * tsx;
-  float acc[(ST * ST + 255) / 256];
-  for (int s = 0; s < (ST * ST + 255) / 256; ++s) acc[s] = 0.f;
+  float acc[(STF * STF + 255) / 256];
+  for (int s = 0; s < (STF * STF + 255) / 256; ++s) acc[s] = 0.f;
   for (int q = 1; q <= 8; ++q) {
     const float* h = filt + (q - 1) * 2 * FILT_STRIDE;
     const float* ucoef = u + size_t(q) * g.N;
@@ -304,7 +305,7 @@ int sara_synthesis(ppd_plan* p, const float* u, float* out) {
     PPD_HIP(hipGetLastError());
     PPD_TRY(timer_end(p, slot));
   }
-  const int tsy = std::min(ST, g.ny), tsx = std::min(ST, g.nx);
+  const int tsy = std::min(STF, g.ny), tsx = std::min(STF, g.nx);
   int slot;
   PPD_TRY(timer_begin(p, KK_IDWT, &slot));
   hipLaunchKernelGGL(k_idwt_final, dim3(g.nx / tsx, g.ny / tsy), dim3(256), 0, p->stream, u, p->sara_rec,
