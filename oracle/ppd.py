@@ -63,13 +63,18 @@ class Params:
 
 
 def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
-            x_true: Optional[np.ndarray] = None, W: Optional[np.ndarray] = None):
+            x_true: Optional[np.ndarray] = None, W: Optional[np.ndarray] = None,
+            trace: Optional[list] = None):
     """Run T iterations of Algorithm 3 in place on ``state``.
 
     op: ``oracle.nufft.Nufft``; y, U: (M,) data and preconditioner; eps: (d,)
     l2 bounds; block_off: (d+1,) contiguous block offsets; W: optional (9, Ny,
     Nx) re-weights (identity when None).  Returns a list of per-iteration
-    records (SNR when x_true is given, relative change, block residuals)."""
+    records (SNR when x_true is given, relative change, block residuals).
+    If ``trace`` is a list, each iteration appends what decides its active
+    sets -- the clip margins |u + Psi^H x~| - alpha, the arguments of P_C and
+    which Algorithm 2 steps project -- i.e. the pieces on which the iteration
+    is smooth."""
     p = params
     y = np.asarray(y, np.complex128)
     U = np.asarray(U, np.float64)
@@ -80,11 +85,19 @@ def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
         v_new = state.v.copy()
         z_new = state.z.copy()
         res = []
+        sets_proj = []
         for j in range(len(block_off) - 1):                # steps 9-13, all blocks
             s = slice(int(block_off[j]), int(block_off[j + 1]))
             res.append(np.linalg.norm(Ga[s] - y[s]))
             w = state.v[s] / U[s] + Ga[s]
             z = prox.fb_ellipsoid(w, y[s], eps[j], U[s], p.mu, p.n_itr, state.z[s])
+            if trace is not None:
+                zz, proj = state.z[s], []
+                for _ in range(p.n_itr):
+                    q = zz - p.mu * U[s] * (zz - w)
+                    proj.append(bool(np.linalg.norm(q - y[s]) > eps[j]))
+                    zz = prox.proj_B(q, y[s], eps[j])
+                sets_proj.append(tuple(proj))
             vbar = U[s] * (w - z)                          # step 10
             v_new[s] = state.v[s] + p.lam * (vbar - state.v[s])   # step 11
             z_new[s] = z
@@ -95,7 +108,11 @@ def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
         ubar = prox.clip_dual(state.u + coef, p.alpha)     # step 19
         u_new = state.u + p.lam * (ubar - state.u)         # step 20
         ut = sara.synthesis(u_new if W is None else W * u_new, p.levels)  # step 21, summed
-        xbar = prox.proj_C(state.x - p.tau * (p.eta * op.ifft_grid_real(vt) + p.zeta * ut))  # step 28
+        arg = state.x - p.tau * (p.eta * op.ifft_grid_real(vt) + p.zeta * ut)
+        xbar = prox.proj_C(arg)                            # step 28
+        if trace is not None:
+            trace.append({"clip": np.abs(state.u + coef) - p.alpha, "pos": arg,
+                          "proj": tuple(sets_proj)})
         x_prev = state.x
         x_new = x_prev + p.lam * (xbar - x_prev)           # step 29
         xt_new = 2.0 * xbar - x_prev                       # step 30

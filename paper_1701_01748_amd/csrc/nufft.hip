@@ -237,6 +237,10 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
       // apply: lane (a, b) owns tap (a, b) of one visibility at a time, so
       // the wave's 64 read-modify-writes touch distinct cells (LDS float
       // atomics are far slower on this part, collisions or not)
+      // Two visibilities per step, even ones into copy A and odd ones into
+      // copy B: two independent read-modify-write chains.  (Summing runs of
+      // visibilities that share a first-tap cell in registers first was
+      // measured slower: the variable-length loop costs more than it saves.)
       const int nb2 = (nb + 1) & ~1;
       for (int k = 0; k < nb2; k += 2) {
         const int pa = __builtin_amdgcn_readlane(pos, k) + lofs;
