@@ -126,6 +126,17 @@ int ppd_phit(ppd_plan* plan, const float* y, float* x, int order);
 int ppd_sara(ppd_plan* plan, int op, const float* in, float* out, float* u_inout,
              float alpha, float lambda);
 
+/* ppd_sara with per-coefficient re-weights W ([9][ny][nx], Sec. 3.2 and
+ * Algorithm 1; NULL = identity): analysis gives W Psi^H in, synthesis
+ * Psi W in, and the dual mode clips u + W Psi^H in and returns Psi W u. */
+int ppd_sara_w(ppd_plan* plan, int op, const float* in, float* out, float* u_inout,
+               const float* W, float alpha, float lambda);
+
+/* Re-weights of Algorithm 1 (eq. reweighting, Sec. 3.2):
+ * W_i = omega / (omega + |Psi_i^H x|) per coefficient, for the image x
+ * ([ny][nx]); W: [9][ny][nx] float32 output.  omega > 0. */
+int ppd_reweight(ppd_plan* plan, const float* x, float omega, float* W);
+
 /* ---- data-fidelity dual: ellipsoid projection (Sec. 4.1, Algorithm 2) -- */
 /* n_itr forward-backward iterations, per block j,
  *     z <- P_B(z - mu U (z - w)),   P_B the projection onto
@@ -177,6 +188,8 @@ typedef struct {
   const double* U;                 /* [M] float64 preconditioner, plan order  */
   const double* eps;               /* HOST [d] l2 bounds                      */
   const float* x_true;             /* optional [ny][nx] reference for SNR     */
+  const float* W;                  /* optional [9][ny][nx] re-weights (Algorithm 1),
+                                      NULL = identity                          */
 } ppd_params;
 
 typedef struct {
@@ -191,9 +204,9 @@ typedef struct {
  * basis is updated each iteration) on `state`.  Step 10 is read as
  * vbar_j = U_j (w_j - prox^U_h(w_j)), w_j = U_j^{-1} v_j + Theta_j G_j a,
  * with the prox approximated by n_itr Algorithm 2 iterations warm-started
- * from state->z.  W_i = I.  If stats (HOST) is non-NULL the call
- * synchronises and fills it (and residual[d], HOST, if non-NULL) from FP64
- * reductions of the last iteration. */
+ * from state->z.  W_i = params->W (identity if NULL).  If stats (HOST) is
+ * non-NULL the call synchronises and fills it (and residual[d], HOST, if
+ * non-NULL) from FP64 reductions of the last iteration. */
 int ppd_iterate(ppd_plan* plan, ppd_state* state, const ppd_params* params, int n_iter,
                 ppd_stats* stats, double* residual);
 

@@ -125,3 +125,27 @@ def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
             rec["snr"] = float(snr_db(x_true, x_new))
         hist.append(rec)
     return hist
+
+
+def reweights(x: np.ndarray, omega: float, levels: int = 3) -> np.ndarray:
+    """Re-weights of Sec. 3.2 (eq. reweighting): omega / (omega + |Psi_i^H x|)."""
+    return omega / (omega + np.abs(sara.analysis(x, levels)))
+
+
+def reweighted(op, y, U, eps, block_off, params: Params, state: State, n_reweights: int,
+               iters_per_solve: int, omega0: float = 1e-2, decay: float = 0.25,
+               x_true: Optional[np.ndarray] = None):
+    """Algorithm 1: Algorithm 3 solves warm-started from the previous state;
+    after solve k the weight parameter becomes omega^(k) = decay^k omega0 and
+    the weights are recomputed from the latest image (the reading of the
+    index of x in the re-weighting equation).  The first solve uses W = I.
+    Returns the per-solve histories and the last weights."""
+    W = None
+    omega = omega0
+    hists = []
+    for k in range(n_reweights + 1):
+        hists.append(iterate(op, y, U, eps, block_off, params, state, iters_per_solve, x_true=x_true, W=W))
+        if k < n_reweights:
+            omega *= decay
+            W = reweights(state.x, omega, params.levels)
+    return hists, W

@@ -117,6 +117,7 @@ struct IterCtx {
   DualArgs dual;
   PrimalArgs primal;
   float* u;
+  const float* W;
   float alpha, lambda;
   int form;
 };
@@ -140,16 +141,16 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
     PPD_TRY(grid_plain(p, c.dual.v));                       // step 12
   }
   PPD_TRY(fft_cols_inverse(p));
-  PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda));        // steps 19-20
-  PPD_TRY(sara_synthesis(p, c.u, p->ut));                   // step 21, summed over i
+  PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda, c.W));   // steps 19-20
+  PPD_TRY(sara_synthesis(p, c.u, p->ut, c.W));              // step 21, summed over i
   return fft_rows_inverse_primal(p, c.primal);              // steps 28-30
 }
 
 std::string graph_key(const IterCtx& c) {
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d",
+  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d",
                 (void*)c.dual.y, (void*)c.dual.U, (void*)c.dual.v, (void*)c.dual.z, (void*)c.primal.x,
-                (void*)c.primal.xt, (void*)c.primal.x_true, (void*)c.u, (void*)c.primal.ut, c.dual.mu,
+                (void*)c.primal.xt, (void*)c.primal.x_true, (void*)c.u, (void*)c.primal.ut, (void*)c.W, c.dual.mu,
                 c.dual.lambda, c.primal.tau, c.primal.eta, c.primal.zeta, double(c.alpha),
                 double(c.lambda), c.dual.n_itr, c.form);
   return std::string(buf);
@@ -208,6 +209,7 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   c.primal.lambda = prm->lambda;
   c.primal.part = p->ppart;
   c.u = st->u;
+  c.W = prm->W;
   c.alpha = float(prm->alpha);
   c.lambda = float(prm->lambda);
   c.form = prm->form;

@@ -170,9 +170,9 @@ int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in);  // dual f
 int plain_dual(ppd_plan* p, const DualArgs& a);               // per-block unfused dual update
 int permute(ppd_plan* p, int direction, const void* in, void* out, int elem_bytes);
 
-int sara_analysis(ppd_plan* p, const float* x, float* coef);
-int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda);
-int sara_synthesis(ppd_plan* p, const float* u, float* out);
+int sara_analysis(ppd_plan* p, const float* x, float* coef, const float* W);
+int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda, const float* W);
+int sara_synthesis(ppd_plan* p, const float* u, float* out, const float* W);
 
 int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq);
 int upload_eps(ppd_plan* p, const double* eps_host);

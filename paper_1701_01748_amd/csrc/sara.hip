@@ -11,6 +11,8 @@
 // Synthesis is the transpose, one launch per level; the last level sums the
 // 8 reconstructions and the Dirac part in registers (no atomics) and applies
 // the 1/3.
+#include <cmath>
+
 #include "ppd_internal.h"
 
 namespace ppd {
@@ -34,7 +36,8 @@ enum { A_PLAIN = 0, A_DUAL = 1 };
 template <int MODE>
 __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float* __restrict__ tmp,
                                              float* __restrict__ out, const float* __restrict__ filt,
-                                             SaraGeom g, int l, float alpha, float lambda) {
+                                             const float* __restrict__ W, SaraGeom g, int l, float alpha,
+                                             float lambda) {
   __shared__ float sin_[MAXR * MAXR];
   __shared__ float slo[AT * MAXR];
   __shared__ float shi[AT * MAXR];
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float*
     for (int i = tid; i < 4 * toy * tox; i += nth) {
       const int a = i / (2 * tox), b = i - a * (2 * tox);
       const size_t P = size_t(2 * k0y + a) * g.nx + (2 * k0x + b);
-      const float c = x[P] * third;
+      const float c = x[P] * third * (W ? W[P] : 1.0f);
       if (MODE == A_PLAIN) {
         out[P] = c;
       } else {
@@ -98,6 +101,7 @@ __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float*
   }
   __syncthreads();
   float* ub = out + size_t(q) * g.N;
+  const float* wb = W ? W + size_t(q) * g.N : nullptr;
   for (int i = tid; i < toy * tox; i += nth) {  // rows (axis 1)
     const int k = i / tox, m = i - k * tox;
     float ll = 0.f, lh = 0.f, hl = 0.f, hh_ = 0.f;
@@ -112,8 +116,8 @@ __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float*
     const size_t pLH = size_t(r) * g.nx + (ow + c);
     const size_t pHL = size_t(oh + r) * g.nx + c;
     const size_t pHH = size_t(oh + r) * g.nx + (ow + c);
-    const float vals[3] = {lh, hl, hh_};
     const size_t pos[3] = {pLH, pHL, pHH};
+    const float vals[3] = {lh * (wb ? wb[pLH] : 1.0f), hl * (wb ? wb[pHL] : 1.0f), hh_ * (wb ? wb[pHH] : 1.0f)};
     for (int s = 0; s < 3; ++s) {
       if (MODE == A_PLAIN) {
         ub[pos[s]] = vals[s];
@@ -125,6 +129,7 @@ __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float*
     }
     if (l == g.L) {
       const size_t pLL = size_t(r) * g.nx + c;
+      if (wb) ll *= wb[pLL];
       if (MODE == A_PLAIN) {
         ub[pLL] = ll;
       } else {
@@ -143,6 +148,7 @@ __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float*
 // thread's loop position) through the functor.
 template <typename Sink>
 __device__ void idwt_tile(const float* __restrict__ llsrc, int llstride, const float* __restrict__ ucoef,
+                          const float* __restrict__ wcoef, const float* __restrict__ llw,
                           int nx, int hh, int ww, int y0, int x0, int tsy, int tsx,
                           const float* __restrict__ h, const float* __restrict__ gh, int taps,
                           float* s_ll, float* s_lh, float* s_hl, float* s_hh, float* s_a, float* s_d,
@@ -155,10 +161,13 @@ __device__ void idwt_tile(const float* __restrict__ llsrc, int llstride, const f
   for (int i = tid; i < KR * KC; i += nth) {
     const int a = i / KC, b = i - a * KC;
     const int r = (krb + a) & (oh - 1), c = (kcb + b) & (ow - 1);
-    s_ll[i] = llsrc[size_t(r) * llstride + c];
-    s_lh[i] = ucoef[size_t(r) * nx + (ow + c)];
-    s_hl[i] = ucoef[size_t(oh + r) * nx + c];
-    s_hh[i] = ucoef[size_t(oh + r) * nx + (ow + c)];
+    const size_t pll = size_t(r) * llstride + c;
+    const size_t plh = size_t(r) * nx + (ow + c), phl = size_t(oh + r) * nx + c;
+    const size_t phh = size_t(oh + r) * nx + (ow + c);
+    s_ll[i] = llsrc[pll] * (llw ? llw[pll] : 1.0f);
+    s_lh[i] = ucoef[plh] * (wcoef ? wcoef[plh] : 1.0f);
+    s_hl[i] = ucoef[phl] * (wcoef ? wcoef[phl] : 1.0f);
+    s_hh[i] = ucoef[phh] * (wcoef ? wcoef[phh] : 1.0f);
   }
   __syncthreads();
   // rows: A = synth(LL, LH), D = synth(HL, HH) along axis 1
@@ -197,7 +206,8 @@ constexpr int SK = ST / 2 + FILT_STRIDE / 2;   // max staged coefficient extent
 
 // Intermediate synthesis level l >= 2 (output = low-pass band of level l-1).
 __global__ __launch_bounds__(256) void k_idwt(const float* __restrict__ u, float* __restrict__ rec,
-                                              const float* __restrict__ filt, SaraGeom g, int l) {
+                                              const float* __restrict__ filt, const float* __restrict__ W,
+                                              SaraGeom g, int l) {
   __shared__ float s_ll[SK * SK], s_lh[SK * SK], s_hl[SK * SK], s_hh[SK * SK];
   __shared__ float s_a[SK * ST], s_d[SK * ST];
   const int hh = g.ny >> (l - 1), ww = g.nx >> (l - 1);
@@ -206,23 +216,27 @@ __global__ __launch_bounds__(256) void k_idwt(const float* __restrict__ u, float
   const int q = blockIdx.z + 1;
   const float* h = filt + (q - 1) * 2 * FILT_STRIDE;
   const float* ucoef = u + size_t(q) * g.N;
+  const float* wcoef = W ? W + size_t(q) * g.N : nullptr;
   const float* llsrc;
+  const float* llw = nullptr;
   int llstride = ww >> 1;
   if (l == g.L) {
     llsrc = ucoef;
+    llw = wcoef;
     llstride = g.nx;
   } else {
     llsrc = rec + g.off[l] + size_t(q - 1) * lvl_size(g, l);
   }
   float* dst = rec + g.off[l - 1] + size_t(q - 1) * lvl_size(g, l - 1);
-  idwt_tile(llsrc, llstride, ucoef, g.nx, hh, ww, y0, x0, tsy, tsx, h, h + FILT_STRIDE, 2 * q,
+  idwt_tile(llsrc, llstride, ucoef, wcoef, llw, g.nx, hh, ww, y0, x0, tsy, tsx, h, h + FILT_STRIDE, 2 * q,
             s_ll, s_lh, s_hl, s_hh, s_a, s_d,
             [&](int, int r, int c, float v) { dst[size_t(y0 + r) * ww + (x0 + c)] = v; });
 }
 
 // Level 1 for all 8 wavelet bases, plus the Dirac part, times 1/3.
 __global__ __launch_bounds__(256) void k_idwt_final(const float* __restrict__ u, const float* __restrict__ rec,
-                                                    const float* __restrict__ filt, SaraGeom g,
+                                                    const float* __restrict__ filt,
+                                                    const float* __restrict__ W, SaraGeom g,
                                                     float* __restrict__ out) {
   __shared__ float s_ll[SK * SK], s_lh[SK * SK], s_hl[SK * SK], s_hh[SK * SK];
   __shared__ float s_a[SK * ST], s_d[SK * ST];
@@ -234,9 +248,11 @@ __global__ __launch_bounds__(256) void k_idwt_final(const float* __restrict__ u,
   for (int q = 1; q <= 8; ++q) {
     const float* h = filt + (q - 1) * 2 * FILT_STRIDE;
     const float* ucoef = u + size_t(q) * g.N;
+    const float* wcoef = W ? W + size_t(q) * g.N : nullptr;
     const float* llsrc = g.L == 1 ? ucoef : rec + g.off[1] + size_t(q - 1) * lvl_size(g, 1);
+    const float* llw = g.L == 1 ? wcoef : nullptr;
     const int llstride = g.L == 1 ? g.nx : (ww >> 1);
-    idwt_tile(llsrc, llstride, ucoef, g.nx, hh, ww, y0, x0, tsy, tsx, h, h + FILT_STRIDE, 2 * q,
+    idwt_tile(llsrc, llstride, ucoef, wcoef, llw, g.nx, hh, ww, y0, x0, tsy, tsx, h, h + FILT_STRIDE, 2 * q,
               s_ll, s_lh, s_hl, s_hh, s_a, s_d,
               [&](int slot, int, int, float v) { acc[slot] += v; });
   }
@@ -245,8 +261,15 @@ __global__ __launch_bounds__(256) void k_idwt_final(const float* __restrict__ u,
   for (int i = threadIdx.x; i < tsy * tsx; i += blockDim.x, ++slot) {
     const int r = i / tsx, c = i - r * tsx;
     const size_t P = size_t(y0 + r) * g.nx + (x0 + c);
-    out[P] = (acc[slot] + u[P]) * third;
+    out[P] = (acc[slot] + u[P] * (W ? W[P] : 1.0f)) * third;
   }
+}
+
+// Algorithm 1 weights (eq. reweighting): W = omega / (omega + |c|), in
+// place over the analysis coefficients c.
+__global__ void k_reweight(float* __restrict__ w, size_t n, float omega) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    w[i] = omega / (omega + fabsf(w[i]));
 }
 
 SaraGeom geom(const ppd_plan* p) {
@@ -263,7 +286,8 @@ SaraGeom geom(const ppd_plan* p) {
   return g;
 }
 
-int analysis_launch(ppd_plan* p, const float* x, float* out, bool dual, float alpha, float lambda) {
+int analysis_launch(ppd_plan* p, const float* x, float* out, const float* W, bool dual, float alpha,
+                    float lambda) {
   const SaraGeom g = geom(p);
   for (int l = 1; l <= g.L; ++l) {
     const int oh = (g.ny >> l), ow = (g.nx >> l);
@@ -272,10 +296,10 @@ int analysis_launch(ppd_plan* p, const float* x, float* out, bool dual, float al
     int slot;
     PPD_TRY(timer_begin(p, KK_DWT, &slot));
     if (dual)
-      hipLaunchKernelGGL(k_dwt<A_DUAL>, grid, dim3(256), 0, p->stream, x, p->sara_ll, out, p->filt, g, l,
+      hipLaunchKernelGGL(k_dwt<A_DUAL>, grid, dim3(256), 0, p->stream, x, p->sara_ll, out, p->filt, W, g, l,
                          alpha, lambda);
     else
-      hipLaunchKernelGGL(k_dwt<A_PLAIN>, grid, dim3(256), 0, p->stream, x, p->sara_ll, out, p->filt, g, l,
+      hipLaunchKernelGGL(k_dwt<A_PLAIN>, grid, dim3(256), 0, p->stream, x, p->sara_ll, out, p->filt, W, g, l,
                          alpha, lambda);
     PPD_HIP(hipGetLastError());
     PPD_TRY(timer_end(p, slot));
@@ -285,15 +309,15 @@ int analysis_launch(ppd_plan* p, const float* x, float* out, bool dual, float al
 
 }  // namespace
 
-int sara_analysis(ppd_plan* p, const float* x, float* coef) {
-  return analysis_launch(p, x, coef, false, 0.f, 0.f);
+int sara_analysis(ppd_plan* p, const float* x, float* coef, const float* W) {
+  return analysis_launch(p, x, coef, W, false, 0.f, 0.f);
 }
 
-int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda) {
-  return analysis_launch(p, x, u, true, alpha, lambda);
+int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda, const float* W) {
+  return analysis_launch(p, x, u, W, true, alpha, lambda);
 }
 
-int sara_synthesis(ppd_plan* p, const float* u, float* out) {
+int sara_synthesis(ppd_plan* p, const float* u, float* out, const float* W) {
   const SaraGeom g = geom(p);
   for (int l = g.L; l >= 2; --l) {
     const int hh = g.ny >> (l - 1), ww = g.nx >> (l - 1);
@@ -301,7 +325,7 @@ int sara_synthesis(ppd_plan* p, const float* u, float* out) {
     int slot;
     PPD_TRY(timer_begin(p, KK_IDWT, &slot));
     hipLaunchKernelGGL(k_idwt, dim3(ww / tsx, hh / tsy, 8), dim3(256), 0, p->stream, u, p->sara_rec, p->filt,
-                       g, l);
+                       W, g, l);
     PPD_HIP(hipGetLastError());
     PPD_TRY(timer_end(p, slot));
   }
@@ -309,7 +333,7 @@ int sara_synthesis(ppd_plan* p, const float* u, float* out) {
   int slot;
   PPD_TRY(timer_begin(p, KK_IDWT, &slot));
   hipLaunchKernelGGL(k_idwt_final, dim3(g.nx / tsx, g.ny / tsy), dim3(256), 0, p->stream, u, p->sara_rec,
-                     p->filt, g, out);
+                     p->filt, W, g, out);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }
@@ -318,20 +342,38 @@ int sara_synthesis(ppd_plan* p, const float* u, float* out) {
 
 using namespace ppd;
 
-extern "C" int ppd_sara(ppd_plan* p, int op, const float* in, float* out, float* u, float alpha,
-                        float lambda) {
+extern "C" int ppd_sara_w(ppd_plan* p, int op, const float* in, float* out, float* u, const float* W,
+                          float alpha, float lambda) {
   if (!p || !in || !out) return fail(PPD_EINVAL, "ppd_sara: NULL argument");
   switch (op) {
     case PPD_SARA_ANALYSIS:
-      return sara_analysis(p, in, out);
+      return sara_analysis(p, in, out, W);
     case PPD_SARA_SYNTHESIS:
-      return sara_synthesis(p, in, out);
+      return sara_synthesis(p, in, out, W);
     case PPD_SARA_DUAL:
       if (!u) return fail(PPD_EINVAL, "ppd_sara: dual mode needs u_inout");
       if (!(alpha >= 0.0f)) return fail(PPD_EINVAL, "ppd_sara: alpha must be >= 0");
-      PPD_TRY(sara_dual(p, in, u, alpha, lambda));
-      return sara_synthesis(p, u, out);
+      PPD_TRY(sara_dual(p, in, u, alpha, lambda, W));
+      return sara_synthesis(p, u, out, W);
     default:
       return fail(PPD_EINVAL, "ppd_sara: unknown op");
   }
+}
+
+extern "C" int ppd_sara(ppd_plan* p, int op, const float* in, float* out, float* u, float alpha,
+                        float lambda) {
+  return ppd_sara_w(p, op, in, out, u, nullptr, alpha, lambda);
+}
+
+extern "C" int ppd_reweight(ppd_plan* p, const float* x, float omega, float* W) {
+  if (!p || !x || !W) return fail(PPD_EINVAL, "ppd_reweight: NULL argument");
+  if (!(omega > 0.0f) || !std::isfinite(omega)) return fail(PPD_EINVAL, "ppd_reweight: omega must be > 0");
+  PPD_TRY(sara_analysis(p, x, W, nullptr));
+  const size_t n = size_t(N_BASES) * p->nx * p->ny;
+  int slot;
+  PPD_TRY(timer_begin(p, KK_MISC, &slot));
+  hipLaunchKernelGGL(k_reweight, dim3(int(std::min<size_t>((n + 255) / 256, 4096))), dim3(256), 0, p->stream, W,
+                     n, omega);
+  PPD_HIP(hipGetLastError());
+  return timer_end(p, slot);
 }

@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
     _fields_ = [("tau", c_double), ("eta", c_double), ("zeta", c_double), ("lambda_", c_double),
                 ("alpha", c_double), ("mu", c_double), ("n_itr", c_int32), ("form", c_int32),
                 ("use_graph", c_int32), ("pad_", c_int32), ("y", c_void_p), ("U", c_void_p),
-                ("eps", ctypes.POINTER(c_double)), ("x_true", c_void_p)]
+                ("eps", ctypes.POINTER(c_double)), ("x_true", c_void_p), ("W", c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -70,6 +70,9 @@ _PROTOS = {
     "ppd_phi": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
     "ppd_phit": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
     "ppd_sara": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float]),
+    "ppd_sara_w": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float,
+                             ctypes.c_float]),
+    "ppd_reweight": (c_int32, [c_void_p, c_void_p, ctypes.c_float, c_void_p]),
     "ppd_ellipsoid_proj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double),
                                      c_int32, c_double, c_void_p]),
     "ppd_uniform_weights": (c_int32, [c_void_p, c_void_p]),
@@ -259,8 +262,11 @@ def ppd_phit(plan: Plan, y, x=None, order: int = ORDER_PLAN):
     return x
 
 
-def ppd_sara(plan: Plan, op: int, inp, out=None, u=None, alpha: float = 0.0, lam: float = 1.0):
+def ppd_sara(plan: Plan, op: int, inp, out=None, u=None, alpha: float = 0.0, lam: float = 1.0, W=None):
+    """SARA analysis / synthesis / dual step (Sec. 5.1), optionally re-weighted (Algorithm 1)."""
     import torch
+    if W is not None:
+        _need(W, torch.float32, 9 * plan.N, "W")
     if op == SARA_ANALYSIS:
         _need(inp, torch.float32, plan.N, "in")
         if out is None:
@@ -279,8 +285,20 @@ def ppd_sara(plan: Plan, op: int, inp, out=None, u=None, alpha: float = 0.0, lam
         _need(out, torch.float32, plan.N, "out")
     else:
         raise ValueError("unknown SARA op")
-    _check("ppd_sara", lib().ppd_sara(plan.handle, op, _ptr(inp), _ptr(out), _ptr(u), float(alpha), float(lam)))
+    _check("ppd_sara", lib().ppd_sara_w(plan.handle, op, _ptr(inp), _ptr(out), _ptr(u), _ptr(W), float(alpha),
+                                         float(lam)))
     return out
+
+
+def ppd_reweight(plan: Plan, x, omega: float, W=None):
+    """Algorithm 1 re-weights W = omega / (omega + |Psi^H x|) ([9][ny][nx])."""
+    import torch
+    _need(x, torch.float32, plan.N, "x")
+    if W is None:
+        W = _alloc((9, plan.ny, plan.nx), torch.float32)
+    _need(W, torch.float32, 9 * plan.N, "W")
+    _check("ppd_reweight", lib().ppd_reweight(plan.handle, _ptr(x), float(omega), _ptr(W)))
+    return W
 
 
 def _eps_arg(plan: Plan, eps):
@@ -348,7 +366,7 @@ class PPDState:
 
 def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49, eta=1.0, zeta=1.0,
                 lam=1.0, alpha=1e-4, mu=1.0, n_itr=1, form=FORM_FUSED, use_graph=False, x_true=None,
-                stats: bool = True):
+                stats: bool = True, W=None):
     """Run n_iter iterations of Algorithm 3; returns a statistics dict (or None)."""
     import torch
     _need(y, torch.complex64, plan.M, "y")
@@ -359,10 +377,12 @@ def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49
         _need(getattr(state, k), dt, n, k)
     if x_true is not None:
         _need(x_true, torch.float32, plan.N, "x_true")
+    if W is not None:
+        _need(W, torch.float32, 9 * plan.N, "W")
     e, ep = _eps_arg(plan, eps)
     st = State(_ptr(state.x), _ptr(state.xt), _ptr(state.v), _ptr(state.u), _ptr(state.z), state.iter)
     prm = Params(tau, eta, zeta, lam, alpha, mu, n_itr, form, int(use_graph), 0, _ptr(y), _ptr(U), ep,
-                 _ptr(x_true))
+                 _ptr(x_true), _ptr(W))
     out = Stats()
     res = (c_double * plan.d)()
     _check("ppd_iterate", lib().ppd_iterate(plan.handle, ctypes.byref(st), ctypes.byref(prm), int(n_iter),
@@ -372,6 +392,23 @@ def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49
         return None
     return {"iter": int(out.iter), "rel_change": out.rel_change, "x_norm": out.x_norm,
             "snr_db": out.snr_db, "residual_max": out.residual_max, "residual": np.array(res[:])}
+
+
+def reweighted_ppd(plan: Plan, state: PPDState, y, U, eps, n_reweights: int, iters_per_solve: int,
+                   omega0: float = 1e-2, decay: float = 0.25, x_true=None, **kw):
+    """Algorithm 1: solve with Algorithm 3 (warm-started from `state`), then
+    omega <- decay * omega and W = omega / (omega + |Psi^H x|), repeated.
+    The first solve uses W = I; the weights of solve k come from solve k-1's
+    image with omega^(k) = decay^k omega0.  Returns per-solve statistics."""
+    W = None
+    omega = omega0
+    out = []
+    for k in range(n_reweights + 1):
+        out.append(ppd_iterate(plan, state, y, U, eps, iters_per_solve, W=W, x_true=x_true, **kw))
+        if k < n_reweights:
+            omega *= decay
+            W = ppd_reweight(plan, state.x, omega, W)
+    return out, W
 
 
 def kb_weights_host(s, kb_beta: float = 0.0) -> np.ndarray:

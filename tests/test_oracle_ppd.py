@@ -160,3 +160,80 @@ def test_input_snr_definition():
     assert pb.sigma ** 2 == pytest.approx(np.mean(np.abs(y0) ** 2) / 100.0, rel=1e-12)
     assert pb.y.dtype == np.complex128
     assert np.array_equal(pb.y, pb.y.astype(np.complex64).astype(np.complex128))
+
+
+# ---- Algorithm 1 re-weighting (Sec. 3.2) ---------------------------------
+
+def test_reweights_dirac_closed_form():
+    """The Dirac basis analyses x to x / 3 under the 1/3-normalised SARA, so
+    its re-weights are omega / (omega + |x| / 3) pixel by pixel."""
+    rng = np.random.default_rng(71)
+    x = rng.standard_normal((32, 32))
+    W = O.reweights(x, 0.05)
+    assert W.shape == (9, 32, 32)
+    assert np.allclose(W[0], 0.05 / (0.05 + np.abs(x) / 3.0), rtol=1e-14, atol=0)
+    assert np.all(W > 0) and np.all(W <= 1.0)
+
+
+def test_reweights_constant_image():
+    """An orthonormal periodised DWT maps a constant image c to zero details
+    and approximation coefficients c 2^levels (sqrt 2 per axis per level):
+    W = 1 at every detail coefficient and omega/(omega + 8c/3) on LL."""
+    c, om = 0.7, 0.1
+    W = O.reweights(np.full((64, 64), c), om)
+    for b in range(1, 9):
+        ll = W[b, :8, :8]
+        assert np.allclose(ll, om / (om + 8.0 * c / 3.0), rtol=1e-12)
+        det = W[b].copy()
+        det[:8, :8] = 1.0
+        assert np.allclose(det, 1.0, rtol=0, atol=1e-12)
+
+
+def test_reweights_limits():
+    rng = np.random.default_rng(72)
+    x = np.abs(rng.standard_normal((32, 32)))
+    assert np.array_equal(O.reweights(np.zeros((32, 32)), 1e-3), np.ones((9, 32, 32)))
+    assert np.allclose(O.reweights(x, 1e12), 1.0, atol=1e-10)
+    small = O.reweights(x, 1e-12)
+    assert small.max() <= 1.0 and np.median(small) < 1e-9
+
+
+def _weighted_problem(seed=73):
+    n, M = 32, 1500
+    x, wu, wv, off = synth.small_case(n, M, seed=seed, d=2)
+    return P.make_problem(x, wu, wv, off, synth.noise_unit(M, seed), 25.0, np.ones((n, n)), power_tol=1e-8)
+
+
+def test_weighted_iteration_identity_and_zero():
+    """W = 1 reproduces the unweighted iteration bit for bit; W = 0 removes
+    the sparsity term: u stays at zero and x follows the iteration with
+    zeta = 0 exactly."""
+    pb = _weighted_problem()
+    n = pb.x_true.shape[0]
+    prm = O.Params(eta=pb.eta)
+    runs = {}
+    for key, W, p in [("none", None, prm), ("ones", np.ones((9, n, n)), prm),
+                      ("zero", np.zeros((9, n, n)), prm), ("zeta0", None, O.Params(eta=pb.eta, zeta=0.0))]:
+        st = O.init_state(n, n, pb.y)
+        O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, p, st, 6, W=W)
+        runs[key] = st
+    assert np.array_equal(runs["ones"].x, runs["none"].x)
+    assert np.array_equal(runs["ones"].u, runs["none"].u)
+    assert np.array_equal(runs["zero"].x, runs["zeta0"].x)
+    assert np.abs(runs["zero"].u).max() == 0.0
+    assert np.abs(runs["none"].u).max() > 0.0
+
+
+def test_reweighted_outer_loop_improves_snr():
+    """Algorithm 1 on the 64x64 workload: each re-weighted solve, warm-started,
+    ends at a higher SNR than the unweighted solve of the same total length
+    (the effect the re-weighting is introduced for, Sec. 3.2)."""
+    w = synth.WORKLOADS["ppd64"]
+    pb = P.problem_from_inputs(synth.make_inputs(w), power_tol=1e-8)
+    prm = O.Params(eta=pb.eta)
+    st = O.init_state(64, 64, pb.y)
+    hists, W = O.reweighted(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, st, 2, 150, x_true=pb.x_true)
+    ref = O.init_state(64, 64, pb.y)
+    h0 = O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, ref, 450, x_true=pb.x_true)
+    assert W.shape == (9, 64, 64) and W.max() <= 1.0
+    assert hists[-1][-1]["snr"] > h0[-1]["snr"]
