@@ -20,56 +20,105 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// One Algorithm 2 iteration over every block, item by item.
+// One Algorithm 2 iteration over every block, item by item (the item's
+// segments flattened into batches of 64, as in the degridding).
 //   mode 0: partials of ||q - y||^2, q = z - mu U (z - w)   (z unchanged)
 //   mode 1: z <- P_B(q) with the block factors, then partials of the next q
 //   mode 2: z <- P_B(q) only
-__global__ __launch_bounds__(256) void k_alg2(
+constexpr int ALG2_WAVES = 4;
+__global__ __launch_bounds__(64 * ALG2_WAVES) void k_alg2(
     int mode, const Item* __restrict__ items, int n_items, const Seg* __restrict__ segs,
     const double2* __restrict__ w, const float2* __restrict__ y, const double* __restrict__ U,
-    double2* __restrict__ z, double mu, const double* __restrict__ part_in,
-    const int32_t* __restrict__ bids, const int32_t* __restrict__ boff, const double* __restrict__ eps,
-    double* __restrict__ part_out) {
-  __shared__ double red[16];
-  __shared__ double s_fac;
-  __shared__ int s_inside;
+    double2* __restrict__ z, double mu, const double2* __restrict__ bfac, double* __restrict__ part_out) {
+  constexpr int NW = ALG2_WAVES;
+  __shared__ ItemTab tab;
+  __shared__ double s_q[NW][MAX_ITEM_SEGS];
   const int ii = xcd_remap(blockIdx.x, gridDim.x);
   if (ii >= n_items) return;
   const Item it = items[ii];
-  for (int s = it.seg0; s < it.seg1; ++s) {
-    const Seg sg = segs[s];
-    double fac = 1.0;
-    bool inside = true;
-    if (mode != 0) {
-      if (threadIdx.x < 64) block_factor(sg.block, part_in, bids, boff, eps, &s_fac, &s_inside);
-      __syncthreads();
-      fac = s_fac;
-      inside = s_inside != 0;
-      __syncthreads();
-    }
+  const int lane = threadIdx.x & 63;
+  const int uwid = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  load_item_tab(it, segs, tab);
+  for (int i = threadIdx.x; i < NW * MAX_ITEM_SEGS; i += blockDim.x) (&s_q[0][0])[i] = 0.0;
+  __syncthreads();
+  const int nseg = it.seg1 - it.seg0;
+  const int total = tab.pre[nseg];
+  int sb = 0;
+  for (int bt = uwid; bt * 64 < total; bt += NW) {
+    while (bt * 64 >= tab.pre[sb + 1]) ++sb;
+    const int li = bt * 64 + lane;
+    const bool act = li < total;
+    const int sg = act ? seg_of(li, sb, tab.pre) : sb;
     double qn = 0.0;
-    for (int k = threadIdx.x; k < sg.count; k += blockDim.x) {
-      const int pi = sg.start + k;
+    if (act) {
+      const int pi = tab.start[sg] + (li - tab.pre[sg]);
       const double2 we = w[pi];
       double2 ze = z[pi];
       const double mU = mu * U[pi];
       const float2 ye = y[pi];
       if (mode != 0) {
+        const double2 bf = bfac[tab.block[sg]];
         const double qx = ze.x - mU * (ze.x - we.x), qy = ze.y - mU * (ze.y - we.y);
-        ze.x = inside ? qx : double(ye.x) + (qx - double(ye.x)) * fac;
-        ze.y = inside ? qy : double(ye.y) + (qy - double(ye.y)) * fac;
+        ze.x = bf.y != 0.0 ? qx : double(ye.x) + (qx - double(ye.x)) * bf.x;
+        ze.y = bf.y != 0.0 ? qy : double(ye.y) + (qy - double(ye.y)) * bf.x;
         z[pi] = ze;
       }
       if (mode != 2) {
         const double dx = (ze.x - mU * (ze.x - we.x)) - double(ye.x);
         const double dy = (ze.y - mU * (ze.y - we.y)) - double(ye.y);
-        qn += dx * dx + dy * dy;
+        qn = dx * dx + dy * dy;
       }
     }
     if (mode != 2) {
-      qn = block_sum(qn, red);
-      if (threadIdx.x == 0) part_out[s] = qn;
+      const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
+      for (int ss = sb; ss <= slast; ++ss) {
+        const double a = wave_sum(act && sg == ss ? qn : 0.0);
+        if (lane == 0) s_q[uwid][ss] += a;
+      }
     }
+  }
+  if (mode != 2) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < nseg; k += blockDim.x) {
+      double q = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < NW; ++wv) q += s_q[wv][k];
+      part_out[it.seg0 + k] = q;
+    }
+  }
+}
+
+// Projection factor of every data block for P_B (Sec. 3.3, eq. proj-L2):
+// workgroup j sums the segment partials of ||q - y_j||^2 in a fixed order
+// and stores (eps_j / r, 0) if r > eps_j, else (1, 1).
+constexpr int BF_PER = 8;
+__global__ __launch_bounds__(256) void k_block_factors(const double* __restrict__ part,
+                                                       const int32_t* __restrict__ bids,
+                                                       const int32_t* __restrict__ boff,
+                                                       const double* __restrict__ eps, double2* __restrict__ bfac) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  const int c0 = boff[j], c1 = boff[j + 1];
+  double s = 0.0;
+  for (int base = c0; base < c1; base += 256 * BF_PER) {
+    int id[BF_PER];
+#pragma unroll
+    for (int k = 0; k < BF_PER; ++k) {
+      const int c = base + int(threadIdx.x) + k * 256;
+      id[k] = c < c1 ? bids[c] : -1;
+    }
+    double v[BF_PER];
+#pragma unroll
+    for (int k = 0; k < BF_PER; ++k) v[k] = id[k] >= 0 ? part[id[k]] : 0.0;
+#pragma unroll
+    for (int k = 0; k < BF_PER; ++k) s += v[k];
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double r = sqrt((red[0] + red[1]) + (red[2] + red[3])), e = eps[j];
+    bfac[j] = r > e ? make_double2(e / r, 0.0) : make_double2(1.0, 1.0);
   }
 }
 
@@ -201,10 +250,20 @@ int grid_blocks(int64_t n) { return int(std::min<int64_t>((n + PL_THREADS - 1) /
 
 int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* y, const double* U, double2* z,
                 double mu, const double* part_in, double* part_out) {
+  if (mode != 0) PPD_TRY(block_factors(p, part_in));
   int slot;
   PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
-  hipLaunchKernelGGL(k_alg2, dim3(p->n_launch), dim3(256), 0, p->stream, mode, p->items, p->n_items,
-                     p->segs, w, y, U, z, mu, part_in, p->bseg_ids, p->bseg_off_d, p->eps_d, part_out);
+  hipLaunchKernelGGL(k_alg2, dim3(p->n_launch), dim3(64 * ALG2_WAVES), 0, p->stream, mode, p->items, p->n_items,
+                     p->segs, w, y, U, z, mu, p->bfac, part_out);
+  PPD_HIP(hipGetLastError());
+  return timer_end(p, slot);
+}
+
+int block_factors(ppd_plan* p, const double* part) {
+  int slot;
+  PPD_TRY(timer_begin(p, KK_MISC, &slot));
+  hipLaunchKernelGGL(k_block_factors, dim3(p->d), dim3(256), 0, p->stream, part, p->bseg_ids, p->bseg_off_d,
+                     p->eps_d, p->bfac);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }

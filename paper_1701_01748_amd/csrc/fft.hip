@@ -19,6 +19,10 @@
 namespace ppd {
 namespace {
 
+// Elements per thread of a staging pass: every launch below has at most
+// 4 * blockDim.x of them (checked on the host).
+constexpr int FFT_PER = 4;
+
 __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }
 __host__ __device__ inline int padded_len(int L) { return L + (L >> 5) + 1; }
 
@@ -86,13 +90,33 @@ __global__ void k_fft_rows_fwd(const float* __restrict__ x, const float* __restr
   float2* tws = sm + rpb * Lp;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int r0 = blockIdx.x * rpb;
-  for (int i = tid; i < (L >> 1); i += nth) tws[i] = tw[i];
+  // all global loads of the thread are issued before the first LDS store
+  float2 twv[FFT_PER];
+  float xv[FFT_PER];
+#pragma unroll
+  for (int k = 0; k < FFT_PER; ++k) {
+    const int i = tid + k * nth;
+    if (i < (L >> 1)) twv[k] = tw[i];
+    if (i < rpb * nx) {
+      const int q = i / nx, c = i - q * nx, r = r0 + q;
+      xv[k] = x[size_t(r) * nx + c] * dpx[c] * dpy[r];
+    }
+  }
   for (int i = tid; i < rpb * Lp; i += nth) sm[i] = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int k = 0; k < FFT_PER; ++k) {
+    const int i = tid + k * nth;
+    if (i < (L >> 1)) tws[i] = twv[k];
+  }
   __syncthreads();
-  for (int i = tid; i < rpb * nx; i += nth) {
-    const int q = i / nx, c = i - q * nx, r = r0 + q;
-    const int n = (c - (nx >> 1)) & (L - 1);
-    sm[q * Lp + padi(bitrev(n, log2L))] = make_float2(x[size_t(r) * nx + c] * dpx[c] * dpy[r], 0.f);
+#pragma unroll
+  for (int k = 0; k < FFT_PER; ++k) {
+    const int i = tid + k * nth;
+    if (i < rpb * nx) {
+      const int q = i / nx, c = i - q * nx;
+      const int n = (c - (nx >> 1)) & (L - 1);
+      sm[q * Lp + padi(bitrev(n, log2L))] = make_float2(xv[k], 0.f);
+    }
   }
   __syncthreads();
   lds_fft<false>(sm, log2L, rpb, Lp, tws);
@@ -113,13 +137,31 @@ __global__ void k_fft_cols_fwd(const float2* __restrict__ half, const float2* __
   float2* tws = sm + C * Lp;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int c0 = grp * C;
-  for (int i = tid; i < (L >> 1); i += nth) tws[i] = tw[i];
+  float2 twv[FFT_PER], hv[FFT_PER];
+#pragma unroll
+  for (int k = 0; k < FFT_PER; ++k) {
+    const int i = tid + k * nth;
+    if (i < (L >> 1)) twv[k] = tw[i];
+    if (i < ny * C) {
+      const int r = i / C, cc = i - r * C;
+      hv[k] = half[size_t(r) * Kx + c0 + cc];
+    }
+  }
   for (int i = tid; i < C * Lp; i += nth) sm[i] = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int k = 0; k < FFT_PER; ++k) {
+    const int i = tid + k * nth;
+    if (i < (L >> 1)) tws[i] = twv[k];
+  }
   __syncthreads();
-  for (int i = tid; i < ny * C; i += nth) {
-    const int r = i / C, cc = i - r * C;
-    const int g = (r - (ny >> 1)) & (L - 1);
-    sm[cc * Lp + padi(bitrev(g, log2L))] = half[size_t(r) * Kx + c0 + cc];
+#pragma unroll
+  for (int k = 0; k < FFT_PER; ++k) {
+    const int i = tid + k * nth;
+    if (i < ny * C) {
+      const int r = i / C, cc = i - r * C;
+      const int g = (r - (ny >> 1)) & (L - 1);
+      sm[cc * Lp + padi(bitrev(g, log2L))] = hv[k];
+    }
   }
   __syncthreads();
   lds_fft<false>(sm, log2L, C, Lp, tws);
@@ -141,10 +183,24 @@ __global__ void k_fft_cols_inv(const float2* __restrict__ grid, const float2* __
   float2* tws = sm + C * Lp;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int c0 = grp * C;
-  for (int i = tid; i < (L >> 1); i += nth) tws[i] = tw[i];
-  for (int i = tid; i < L * C; i += nth) {
-    const int g = i / C, cc = i - g * C;
-    sm[cc * Lp + padi(bitrev(g, log2L))] = grid[size_t(g) * Kx + c0 + cc];
+  float2 twv[FFT_PER], gv[FFT_PER];
+#pragma unroll
+  for (int k = 0; k < FFT_PER; ++k) {
+    const int i = tid + k * nth;
+    if (i < (L >> 1)) twv[k] = tw[i];
+    if (i < L * C) {
+      const int g = i / C, cc = i - g * C;
+      gv[k] = grid[size_t(g) * Kx + c0 + cc];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < FFT_PER; ++k) {
+    const int i = tid + k * nth;
+    if (i < (L >> 1)) tws[i] = twv[k];
+    if (i < L * C) {
+      const int g = i / C, cc = i - g * C;
+      sm[cc * Lp + padi(bitrev(g, log2L))] = gv[k];
+    }
   }
   __syncthreads();
   lds_fft<true>(sm, log2L, C, Lp, tws);
@@ -182,10 +238,18 @@ __global__ void k_fft_rows_inv(const float2* __restrict__ half, const float2* __
   float2* tws = sm + rpb * Lp;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int r0 = blockIdx.x * rpb;
-  for (int i = tid; i < (L >> 1); i += nth) tws[i] = tw[i];
-  for (int i = tid; i < rpb * L; i += nth) {
-    const int q = i >> log2L, k = i & (L - 1);
-    sm[q * Lp + padi(bitrev(k, log2L))] = half[size_t(r0 + q) * L + k];
+  float2 twv[FFT_PER], hv[FFT_PER];
+#pragma unroll
+  for (int k = 0; k < FFT_PER; ++k) {
+    const int i = tid + k * nth;
+    if (i < (L >> 1)) twv[k] = tw[i];
+    if (i < rpb * L) hv[k] = half[size_t(r0 + (i >> log2L)) * L + (i & (L - 1))];
+  }
+#pragma unroll
+  for (int k = 0; k < FFT_PER; ++k) {
+    const int i = tid + k * nth;
+    if (i < (L >> 1)) tws[i] = twv[k];
+    if (i < rpb * L) sm[(i >> log2L) * Lp + padi(bitrev(i & (L - 1), log2L))] = hv[k];
   }
   __syncthreads();
   lds_fft<true>(sm, log2L, rpb, Lp, tws);
@@ -229,8 +293,8 @@ __global__ void k_fft_rows_inv(const float2* __restrict__ half, const float2* __
   }
 }
 
-struct RowCfg { int rpb, threads, blocks; size_t lds; };
-struct ColCfg { int C, threads, ngroups, blocks; size_t lds; };
+struct RowCfg { int rpb, threads, blocks; size_t lds; bool ok; };
+struct ColCfg { int C, threads, ngroups, blocks; size_t lds; bool ok; };
 
 RowCfg row_cfg(int L, int rows) {
   RowCfg c;
@@ -239,6 +303,7 @@ RowCfg row_cfg(int L, int rows) {
   c.threads = std::min(1024, std::max(64, c.rpb * L / 4));
   c.blocks = rows / c.rpb;
   c.lds = (size_t(c.rpb) * padded_len(L) + L / 2) * sizeof(float2);
+  c.ok = c.rpb * L <= FFT_PER * c.threads && L / 2 <= FFT_PER * c.threads;
   return c;
 }
 
@@ -250,6 +315,7 @@ ColCfg col_cfg(int L, int Kx) {
   c.ngroups = Kx / c.C;
   c.blocks = ((c.ngroups + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
   c.lds = (size_t(c.C) * padded_len(L) + L / 2) * sizeof(float2);
+  c.ok = c.C * L <= FFT_PER * c.threads && L / 2 <= FFT_PER * c.threads;
   return c;
 }
 
@@ -258,12 +324,14 @@ ColCfg col_cfg(int L, int Kx) {
 int fft_forward(ppd_plan* p, const float* x) {
   int slot;
   const RowCfg rc = row_cfg(p->Kx, p->ny);
+  if (!rc.ok) return fail(PPD_EUNSUPPORTED, "fft: row launch shape exceeds the staging capacity");
   PPD_TRY(timer_begin(p, KK_FFT_ROWS_FWD, &slot));
   hipLaunchKernelGGL(k_fft_rows_fwd, dim3(rc.blocks), dim3(rc.threads), rc.lds, p->stream, x, p->dpx,
                      p->dpy, p->twx, p->nx, p->log2Kx, rc.rpb, p->half);
   PPD_HIP(hipGetLastError());
   PPD_TRY(timer_end(p, slot));
   const ColCfg cc = col_cfg(p->Ky, p->Kx);
+  if (!cc.ok) return fail(PPD_EUNSUPPORTED, "fft: column launch shape exceeds the staging capacity");
   PPD_TRY(timer_begin(p, KK_FFT_COLS_FWD, &slot));
   hipLaunchKernelGGL(k_fft_cols_fwd, dim3(cc.blocks), dim3(cc.threads), cc.lds, p->stream, p->half,
                      p->twy, p->ny, p->Kx, p->log2Ky, cc.C, cc.ngroups, p->grid_f);
@@ -275,6 +343,7 @@ int fft_forward(ppd_plan* p, const float* x) {
 int fft_cols_inverse(ppd_plan* p) {
   int slot;
   const ColCfg cc = col_cfg(p->Ky, p->Kx);
+  if (!cc.ok) return fail(PPD_EUNSUPPORTED, "fft: column launch shape exceeds the staging capacity");
   PPD_TRY(timer_begin(p, KK_FFT_COLS_INV, &slot));
   hipLaunchKernelGGL(k_fft_cols_inv, dim3(cc.blocks), dim3(cc.threads), cc.lds, p->stream, p->grid_a,
                      p->twy, p->ny, p->Kx, p->log2Ky, cc.C, cc.ngroups, p->half);
@@ -287,6 +356,7 @@ int fft_adjoint(ppd_plan* p, float* x) {
   PPD_TRY(fft_cols_inverse(p));
   int slot;
   const RowCfg rc = row_cfg(p->Kx, p->ny);
+  if (!rc.ok) return fail(PPD_EUNSUPPORTED, "fft: row launch shape exceeds the staging capacity");
   PPD_TRY(timer_begin(p, KK_FFT_ROWS_INV, &slot));
   hipLaunchKernelGGL(k_fft_rows_inv<false>, dim3(rc.blocks), dim3(rc.threads), rc.lds, p->stream,
                      p->half, p->twx, p->dpx, p->dpy, p->nx, p->log2Kx, rc.rpb, x, nullptr, nullptr,
@@ -299,6 +369,7 @@ int fft_adjoint(ppd_plan* p, float* x) {
 int fft_rows_inverse_primal(ppd_plan* p, const PrimalArgs& a) {
   int slot;
   const RowCfg rc = row_cfg(p->Kx, p->ny);
+  if (!rc.ok) return fail(PPD_EUNSUPPORTED, "fft: row launch shape exceeds the staging capacity");
   PPD_TRY(timer_begin(p, KK_FFT_ROWS_INV, &slot));
   hipLaunchKernelGGL(k_fft_rows_inv<true>, dim3(rc.blocks), dim3(rc.threads), rc.lds, p->stream,
                      p->half, p->twx, p->dpx, p->dpy, p->nx, p->log2Kx, rc.rpb, a.x, a.xt, a.ut,

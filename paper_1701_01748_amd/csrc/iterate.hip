@@ -122,9 +122,29 @@ struct IterCtx {
   int form;
 };
 
+// Runs the plan's launches on another stream for the lifetime of the object.
+struct OnStream {
+  ppd_plan* p;
+  hipStream_t saved;
+  OnStream(ppd_plan* pl, hipStream_t s) : p(pl), saved(pl->stream) { p->stream = s; }
+  ~OnStream() { p->stream = saved; }
+};
+
 // One iteration of Algorithm 3 (no randomisation) on the plan's stream.
+// Steps 19-21 (SARA dual update and synthesis) need only x~ and u, so they
+// are forked to the plan's second stream and run concurrently with the
+// data-fidelity path (steps 4-12); the primal update (steps 28-30) waits for
+// both.  Under graph capture the fork and join become edges of the graph.
 int one_iteration(ppd_plan* p, const IterCtx& c) {
   const float* xt = c.primal.xt;
+  PPD_HIP(hipEventRecord(p->ev_fork, p->stream));
+  PPD_HIP(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
+  {
+    OnStream on(p, p->aux);
+    PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda, c.W));   // steps 19-20
+    PPD_TRY(sara_synthesis(p, c.u, p->ut, c.W));              // step 21, summed over i
+    PPD_HIP(hipEventRecord(p->ev_join, p->aux));
+  }
   PPD_TRY(fft_forward(p, xt));                              // step 4: a = F Z x~
   if (c.form == PPD_FORM_FUSED) {
     double* pa = p->part;
@@ -141,8 +161,7 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
     PPD_TRY(grid_plain(p, c.dual.v));                       // step 12
   }
   PPD_TRY(fft_cols_inverse(p));
-  PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda, c.W));   // steps 19-20
-  PPD_TRY(sara_synthesis(p, c.u, p->ut, c.W));              // step 21, summed over i
+  PPD_HIP(hipStreamWaitEvent(p->stream, p->ev_join, 0));
   return fft_rows_inverse_primal(p, c.primal);              // steps 28-30
 }
 

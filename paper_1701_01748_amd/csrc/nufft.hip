@@ -2,8 +2,9 @@
 // kernels), with the data-block dual update of Algorithm 3 fused in.
 //
 // Work item: up to chunk_max visibilities whose first tap lies in one
-// T x T grid tile, as per-block segments.  The workgroup works on the tile
-// plus its 7-cell halo, (T+7)^2 complex cells, in LDS:
+// T x T grid tile, as per-block segments (at most 64), flattened into one
+// range and taken in batches of 64.  The workgroup works on the tile plus
+// its 7-cell halo, (T+7)^2 complex cells, in LDS:
 //   degrid: the forward spectrum region is copied in, each thread then
 //           interpolates its visibilities from LDS (64 taps each);
 //   grid:   each wave owns a private copy of the region; a batch of 64
@@ -22,17 +23,6 @@
 
 namespace ppd {
 namespace {
-
-__device__ inline double block_sum(double v, double* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < nw; ++w) s += red[w];
-  return s;
-}
 
 struct Taps {
   int ou, ov;         // first tap relative to the staged region
@@ -53,8 +43,16 @@ __device__ __forceinline__ void taps_for(float omu, float omv, double su, double
   kb_weights(float(tv - fv), coef, t.wy);
 }
 
+constexpr int DEGRID_WAVES = 4;
+
+// Degridding: one workgroup per item, the region staged in LDS; the item's
+// visibilities (all its segments, flattened) are taken in batches of 64, a
+// batch per wave in turn, one visibility per lane.  In the dual mode the
+// per-segment partials of ||q - y||^2 and ||G a - y||^2 are wave sums over
+// the lanes of each segment, added per wave in batch order and summed over
+// the waves in a fixed order at the end: deterministic.
 template <int T, bool DUAL>
-__global__ __launch_bounds__(256) void k_degrid(
+__global__ __launch_bounds__(64 * DEGRID_WAVES) void k_degrid(
     const float2* __restrict__ grid, int Kx, int Ky, const Item* __restrict__ items, int n_items,
     const Seg* __restrict__ segs, const float* __restrict__ wu, const float* __restrict__ wv,
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
@@ -62,26 +60,88 @@ __global__ __launch_bounds__(256) void k_degrid(
     const float2* __restrict__ v, const double2* __restrict__ z, double2* __restrict__ wout, double mu,
     double* __restrict__ part, double* __restrict__ rpart) {
   constexpr int R = T + 7;
+  constexpr int NW = DEGRID_WAVES;
   __shared__ float2 reg[R * R];
   __shared__ float coef[KB_TAPS * KB_NC];
-  __shared__ double red[16];
+  __shared__ ItemTab tab;
+  __shared__ double s_q[NW][MAX_ITEM_SEGS], s_r[NW][MAX_ITEM_SEGS];
   const int ii = xcd_remap(blockIdx.x, gridDim.x);
   if (ii >= n_items) return;
   const Item it = items[ii];
   const int r0 = it.ty * T, c0 = it.tx * T;
-  for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
-    const int a = i / R, b = i - a * R;
-    reg[i] = grid[size_t((r0 + a) & (Ky - 1)) * Kx + ((c0 + b) & (Kx - 1))];
+  const int lane = threadIdx.x & 63;
+  const int uwid = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  // staging: all of the thread's loads are issued before its LDS stores
+  constexpr int RPT = (R * R + 64 * NW - 1) / (64 * NW);
+  float2 gv[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = threadIdx.x + k * 64 * NW;
+    if (i < R * R) {
+      const int a = i / R, b = i - a * R;
+      gv[k] = grid[size_t((r0 + a) & (Ky - 1)) * Kx + ((c0 + b) & (Kx - 1))];
+    }
   }
+  load_item_tab(it, segs, tab);
   for (int i = threadIdx.x; i < KB_TAPS * KB_NC; i += blockDim.x) coef[i] = kbc[i];
+  if (DUAL)
+    for (int i = threadIdx.x; i < NW * MAX_ITEM_SEGS; i += blockDim.x) {
+      (&s_q[0][0])[i] = 0.0;
+      (&s_r[0][0])[i] = 0.0;
+    }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = threadIdx.x + k * 64 * NW;
+    if (i < R * R) reg[i] = gv[k];
+  }
   __syncthreads();
-  for (int s = it.seg0; s < it.seg1; ++s) {
-    const Seg sg = segs[s];
+  const int nseg = it.seg1 - it.seg0;
+  const int total = tab.pre[nseg];
+  // Batch k of 64 flattened visibilities goes to wave k mod NW; a wave
+  // loads its next batch's operands before working on the current one.
+  struct Batch {
+    float ou, ov, th;
+    float2 v, y;
+    double2 z;
+    double U;
+    int pi, sg, sb;
+  };
+  auto load = [&](int bt, int& sb, Batch& b) {
+    while (bt * 64 >= tab.pre[sb + 1]) ++sb;
+    b.sb = sb;
+    const int li = bt * 64 + lane;
+    b.sg = sb;
+    if (li < total) {
+      b.sg = seg_of(li, sb, tab.pre);
+      b.pi = tab.start[b.sg] + (li - tab.pre[b.sg]);
+      b.ou = wu[b.pi];
+      b.ov = wv[b.pi];
+      b.th = theta ? theta[b.pi] : 1.0f;
+      if (DUAL) {
+        b.v = v[b.pi];
+        b.U = U[b.pi];
+        b.z = z[b.pi];
+        b.y = y[b.pi];
+      }
+    }
+  };
+  int sbl = 0;
+  Batch bn{};
+  if (uwid * 64 < total) load(uwid, sbl, bn);
+  for (int bt = uwid; bt * 64 < total; bt += NW) {
+    const Batch cb = bn;
+    if ((bt + NW) * 64 < total) load(bt + NW, sbl, bn);
+    const int li = bt * 64 + lane;
+    const bool act = li < total;
+    const int sb = __builtin_amdgcn_readfirstlane(cb.sb), sg = cb.sg, pi = cb.pi;
     double qn = 0.0, rn = 0.0;
-    for (int k = threadIdx.x; k < sg.count; k += blockDim.x) {
-      const int pi = sg.start + k;
+    if (act) {
+      const float omu = cb.ou, omv = cb.ov, th = cb.th;
+      const float2 ve = cb.v, ye = cb.y;
+      const double Ue = DUAL ? cb.U : 1.0;
+      const double2 ze = cb.z;
       Taps t;
-      taps_for<T>(wu[pi], wv[pi], su, sv, Kx, Ky, c0, r0, coef, t);
+      taps_for<T>(omu, omv, su, sv, Kx, Ky, c0, r0, coef, t);
       float ax = 0.f, ay = 0.f;
 #pragma unroll 2
       for (int a = 0; a < KB_TAPS; ++a) {
@@ -98,34 +158,45 @@ __global__ __launch_bounds__(256) void k_degrid(
         ax = fmaf(wya, sx, ax);
         ay = fmaf(wya, sy, ay);
       }
-      const float th = theta ? theta[pi] : 1.0f;
       const float2 g = make_float2(ax * th, ay * th);
       if (!DUAL) {
         out[pi] = g;
       } else {
         // Algorithm 3 step 10: w = U^-1 v + Theta G a; first Algorithm 2 step
-        const float2 ve = v[pi];
-        const double Ue = U[pi];
-        const double2 ze = z[pi];
-        const float2 ye = y[pi];
         const double wx = double(ve.x) / Ue + double(g.x);
         const double wy = double(ve.y) / Ue + double(g.y);
         wout[pi] = make_double2(wx, wy);
         const double mU = mu * Ue;
         const double dx = (ze.x - mU * (ze.x - wx)) - double(ye.x);
         const double dy = (ze.y - mU * (ze.y - wy)) - double(ye.y);
-        qn += dx * dx + dy * dy;
+        qn = dx * dx + dy * dy;
         const double ex = double(g.x) - double(ye.x), ey = double(g.y) - double(ye.y);
-        rn += ex * ex + ey * ey;
+        rn = ex * ex + ey * ey;
       }
     }
     if (DUAL) {
-      qn = block_sum(qn, red);
-      rn = block_sum(rn, red);
-      if (threadIdx.x == 0) {
-        part[s] = qn;
-        rpart[s] = rn;
+      const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
+      for (int ss = sb; ss <= slast; ++ss) {
+        const double a = wave_sum(act && sg == ss ? qn : 0.0);
+        const double r = wave_sum(act && sg == ss ? rn : 0.0);
+        if (lane == 0) {
+          s_q[uwid][ss] += a;
+          s_r[uwid][ss] += r;
+        }
       }
+    }
+  }
+  if (DUAL) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < nseg; k += blockDim.x) {
+      double q = 0.0, r = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        q += s_q[w][k];
+        r += s_r[w][k];
+      }
+      part[it.seg0 + k] = q;
+      rpart[it.seg0 + k] = r;
     }
   }
 }
@@ -148,22 +219,23 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
     const float2* __restrict__ vin, const float2* __restrict__ y, const double* __restrict__ U,
     float2* __restrict__ v, double2* __restrict__ z, const double2* __restrict__ w, double mu,
-    double lambda, const double* __restrict__ part, const int32_t* __restrict__ bids,
-    const int32_t* __restrict__ boff, const double* __restrict__ eps) {
+    double lambda, const double2* __restrict__ bfac) {
   constexpr int R = GridCfg<T>::R;
   constexpr int NW = GridCfg<T>::NW;
   __shared__ float2 acc_a[NW][R * R];
   __shared__ float2 acc_b[NW][R * R];
-  __shared__ float2 wxv[NW][64 * KB_TAPS];   // wx[b] * value, per visibility of the batch
-  __shared__ float wyb[NW][64 * KB_TAPS];    // wy[a]
+  constexpr int WXS = KB_TAPS + 1;             // staging stride per visibility (bank spread)
+  __shared__ float2 wxv[NW][64 * WXS];         // wx[b] * value, per visibility of the batch
+  __shared__ float wyb[NW][64 * WXS];          // wy[a]
   __shared__ float coef[KB_TAPS * KB_NC];
-  __shared__ double s_fac;
-  __shared__ int s_inside;
+  __shared__ ItemTab tab;
   const int ii = xcd_remap(blockIdx.x, gridDim.x);
   if (ii >= n_items) return;
   const Item it = items[ii];
   const int r0 = it.ty * T, c0 = it.tx * T;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int uwid = __builtin_amdgcn_readfirstlane(wid);   // wave-uniform
+  load_item_tab(it, segs, tab);
   for (int i = threadIdx.x; i < NW * R * R; i += blockDim.x) {
     (&acc_a[0][0])[i] = make_float2(0.f, 0.f);
     (&acc_b[0][0])[i] = make_float2(0.f, 0.f);
@@ -176,87 +248,118 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
   float* mywy = wyb[wid];
   const int ta = lane >> 3, tb = lane & 7;   // tap of this lane in the apply phase
   const int lofs = ta * R + tb;
-  for (int s = it.seg0; s < it.seg1; ++s) {
-    const Seg sg = segs[s];
-    double fac = 1.0;
-    bool inside = true;
-    if (DUAL) {
-      if (threadIdx.x < 64) block_factor(sg.block, part, bids, boff, eps, &s_fac, &s_inside);
-      __syncthreads();
-      fac = s_fac;
-      inside = s_inside != 0;
-      __syncthreads();
-    }
-    const int q = (sg.count + NW - 1) / NW;
-    const int k0 = min(wid * q, sg.count), k1 = min(k0 + q, sg.count);
-    for (int base = k0; base < k1; base += 64) {
-      const int nb = min(64, k1 - base);
-      // prepare: one visibility per lane (lanes past nb carry zero weight)
-      int pos = 0;
-      float vx = 0.f, vy = 0.f;
-      Taps t;
-      if (lane < nb) {
-        const int pi = sg.start + base + lane;
-        taps_for<T>(wu[pi], wv[pi], su, sv, Kx, Ky, c0, r0, coef, t);
-        float2 val;
-        if (!DUAL) {
-          val = vin[pi];
-        } else {
-          // last Algorithm 2 projection z = P_B(q), then steps 10-11
-          const double2 we = w[pi], ze = z[pi];
-          const double Ue = U[pi];
-          const float2 ye = y[pi], vo = v[pi];
-          const double mU = mu * Ue;
-          const double qx = ze.x - mU * (ze.x - we.x), qy = ze.y - mU * (ze.y - we.y);
-          const double zx = inside ? qx : double(ye.x) + (qx - double(ye.x)) * fac;
-          const double zy = inside ? qy : double(ye.y) + (qy - double(ye.y)) * fac;
-          z[pi] = make_double2(zx, zy);
-          const double vbx = Ue * (we.x - zx), vby = Ue * (we.y - zy);
-          const float2 vn = make_float2(float(double(vo.x) + lambda * (vbx - double(vo.x))),
-                                        float(double(vo.y) + lambda * (vby - double(vo.y))));
-          v[pi] = vn;
-          val = vn;
-        }
-        const float th = theta ? theta[pi] : 1.0f;
-        vx = val.x * th;
-        vy = val.y * th;
-        pos = t.ov * R + t.ou;
+  // The item's visibilities (all segments, flattened) are taken in batches
+  // of 64, batch k by wave k mod NW.  The global operands of a wave's next
+  // batch are loaded before its current batch is prepared and applied, so
+  // their latency overlaps the LDS work.
+  struct Batch {
+    float ou, ov, th;
+    float2 vin, y, v;
+    double2 w, z, bf;
+    double U;
+    int pi;
+  };
+  const int nseg = it.seg1 - it.seg0;
+  const int total = tab.pre[nseg];
+  auto load = [&](int bt, int& sb, Batch& b) {
+    while (bt * 64 >= tab.pre[sb + 1]) ++sb;
+    const int li = bt * 64 + lane;
+    if (li < total) {
+      const int sg = seg_of(li, sb, tab.pre);
+      const int pi = tab.start[sg] + (li - tab.pre[sg]);
+      b.pi = pi;
+      b.ou = wu[pi];
+      b.ov = wv[pi];
+      b.th = theta ? theta[pi] : 1.0f;
+      if (!DUAL) {
+        b.vin = vin[pi];
       } else {
-#pragma unroll
-        for (int m = 0; m < KB_TAPS; ++m) {
-          t.wx[m] = 0.f;
-          t.wy[m] = 0.f;
-        }
+        b.w = w[pi];
+        b.z = z[pi];
+        b.U = U[pi];
+        b.y = y[pi];
+        b.v = v[pi];
+        b.bf = bfac[tab.block[sg]];
       }
+    }
+  };
+  int sb = 0;
+  Batch bn{};
+  if (uwid * 64 < total) load(uwid, sb, bn);
+  for (int k = uwid; k * 64 < total; k += NW) {
+    const Batch bt = bn;
+    if ((k + NW) * 64 < total) load(k + NW, sb, bn);
+    const int nb = min(64, total - k * 64);
+    // prepare: one visibility per lane (lanes past nb carry zero weight).
+    // The new z and v are stored after the apply loop, so that no store is
+    // in flight (and waited for) while the loop runs.
+    double2 znew{};
+    float2 vnew{};
+    int pos = 0;
+    float vx = 0.f, vy = 0.f;
+    Taps t;
+    if (lane < nb) {
+      taps_for<T>(bt.ou, bt.ov, su, sv, Kx, Ky, c0, r0, coef, t);
+      float2 val;
+      if (!DUAL) {
+        val = bt.vin;
+      } else {
+        // last Algorithm 2 projection z = P_B(q) with the block's factor,
+        // then steps 10-11
+        const double fac = bt.bf.x;
+        const bool inside = bt.bf.y != 0.0;
+        const double mU = mu * bt.U;
+        const double qx = bt.z.x - mU * (bt.z.x - bt.w.x), qy = bt.z.y - mU * (bt.z.y - bt.w.y);
+        const double zx = inside ? qx : double(bt.y.x) + (qx - double(bt.y.x)) * fac;
+        const double zy = inside ? qy : double(bt.y.y) + (qy - double(bt.y.y)) * fac;
+        znew = make_double2(zx, zy);
+        const double vbx = bt.U * (bt.w.x - zx), vby = bt.U * (bt.w.y - zy);
+        const float2 vn = make_float2(float(double(bt.v.x) + lambda * (vbx - double(bt.v.x))),
+                                      float(double(bt.v.y) + lambda * (vby - double(bt.v.y))));
+        vnew = vn;
+        val = vn;
+      }
+      vx = val.x * bt.th;
+      vy = val.y * bt.th;
+      pos = t.ov * R + t.ou;
+    } else {
 #pragma unroll
       for (int m = 0; m < KB_TAPS; ++m) {
-        mywxv[lane * KB_TAPS + m] = make_float2(t.wx[m] * vx, t.wx[m] * vy);
-        mywy[lane * KB_TAPS + m] = t.wy[m];
+        t.wx[m] = 0.f;
+        t.wy[m] = 0.f;
       }
-      __builtin_amdgcn_wave_barrier();
-      // apply: lane (a, b) owns tap (a, b) of one visibility at a time, so
-      // the wave's 64 read-modify-writes touch distinct cells (LDS float
-      // atomics are far slower on this part, collisions or not)
-      // Two visibilities per step, even ones into copy A and odd ones into
-      // copy B: two independent read-modify-write chains.  (Summing runs of
-      // visibilities that share a first-tap cell in registers first was
-      // measured slower: the variable-length loop costs more than it saves.)
-      const int nb2 = (nb + 1) & ~1;
-      for (int k = 0; k < nb2; k += 2) {
-        const int pa = __builtin_amdgcn_readlane(pos, k) + lofs;
-        const int pb = __builtin_amdgcn_readlane(pos, k + 1) + lofs;
-        const float2 xa = mywxv[k * KB_TAPS + tb], xb = mywxv[(k + 1) * KB_TAPS + tb];
-        const float ga = mywy[k * KB_TAPS + ta], gb = mywy[(k + 1) * KB_TAPS + ta];
-        float2 ca = accA[pa];
-        float2 cb = accB[pb];
-        ca.x = fmaf(ga, xa.x, ca.x);
-        ca.y = fmaf(ga, xa.y, ca.y);
-        cb.x = fmaf(gb, xb.x, cb.x);
-        cb.y = fmaf(gb, xb.y, cb.y);
-        accA[pa] = ca;
-        accB[pb] = cb;
-      }
-      __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int m = 0; m < KB_TAPS; ++m) {
+      mywxv[lane * WXS + m] = make_float2(t.wx[m] * vx, t.wx[m] * vy);
+      mywy[lane * WXS + m] = t.wy[m];
+    }
+    __builtin_amdgcn_wave_barrier();
+    // apply: lane (a, b) owns tap (a, b) of one visibility at a time, so
+    // the wave's 64 read-modify-writes touch distinct cells (LDS float
+    // atomics are far slower on this part, collisions or not).
+    // Two visibilities per step, even ones into copy A and odd ones into
+    // copy B: two independent read-modify-write chains.  (Register
+    // accumulation over visibilities sharing a cell was measured slower.)
+    const int nb2 = (nb + 1) & ~1;
+    for (int k = 0; k < nb2; k += 2) {
+      const int pa = __builtin_amdgcn_readlane(pos, k) + lofs;
+      const int pb = __builtin_amdgcn_readlane(pos, k + 1) + lofs;
+      const float2 xa = mywxv[k * WXS + tb], xb = mywxv[(k + 1) * WXS + tb];
+      const float ga = mywy[k * WXS + ta], gb = mywy[(k + 1) * WXS + ta];
+      float2 ca = accA[pa];
+      float2 cb = accB[pb];
+      ca.x = fmaf(ga, xa.x, ca.x);
+      ca.y = fmaf(ga, xa.y, ca.y);
+      cb.x = fmaf(gb, xb.x, cb.x);
+      cb.y = fmaf(gb, xb.y, cb.y);
+      accA[pa] = ca;
+      accB[pb] = cb;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (DUAL && lane < nb) {
+      z[bt.pi] = znew;
+      v[bt.pi] = vnew;
     }
   }
   __syncthreads();
@@ -331,12 +434,12 @@ __global__ void k_permute(const int32_t* __restrict__ perm, int64_t M, int to_us
 template <int T>
 int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double* part_out) {
   if (!dual) {
-    hipLaunchKernelGGL((k_degrid<T, false>), dim3(p->n_launch), dim3(256), 0, p->stream, p->grid_f,
+    hipLaunchKernelGGL((k_degrid<T, false>), dim3(p->n_launch), dim3(64 * DEGRID_WAVES), 0, p->stream, p->grid_f,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, out, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0,
                        nullptr, nullptr);
   } else {
-    hipLaunchKernelGGL((k_degrid<T, true>), dim3(p->n_launch), dim3(256), 0, p->stream, p->grid_f,
+    hipLaunchKernelGGL((k_degrid<T, true>), dim3(p->n_launch), dim3(64 * DEGRID_WAVES), 0, p->stream, p->grid_f,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->wbuf, a->mu,
                        part_out, p->rpart);
@@ -351,12 +454,12 @@ int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, co
     hipLaunchKernelGGL((k_grid<T, false>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, vin, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0,
-                       0.0, nullptr, nullptr, nullptr, nullptr);
+                       0.0, nullptr);
   } else {
     hipLaunchKernelGGL((k_grid<T, true>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->wbuf, a->mu,
-                       a->lambda, part_in, p->bseg_ids, p->bseg_off_d, p->eps_d);
+                       a->lambda, p->bfac);
   }
   PPD_HIP(hipGetLastError());
   return PPD_OK;
@@ -411,6 +514,7 @@ int grid_plain(ppd_plan* p, const float2* v) {
 }
 
 int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in) {
+  PPD_TRY(block_factors(p, part_in));
   PPD_TRY(dispatch_grid(p, true, nullptr, &a, part_in));
   return fold_grid(p);
 }

@@ -201,7 +201,11 @@ static void destroy_plan(ppd_plan* p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->aux) (void)hipStreamSynchronize(p->aux);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
   for (void* q : p->allocations) (void)hipFree(q);
   delete p;
 }
@@ -334,21 +338,23 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
     for (const Bin& b : tile_bins[t]) total += b.count;
     tile_item_off[t] = int32_t(items.size());
     if (total == 0) continue;
-    const int64_t nit = (total + chunk_max - 1) / chunk_max;
     size_t bi = 0;
     int64_t used = 0;   // visibilities of tile_bins[t][bi] already assigned
-    for (int64_t k = 0; k < nit; ++k) {
-      int64_t want = total * (k + 1) / nit - total * k / nit;
+    int64_t left = total;
+    while (left > 0) {
+      const int64_t nit = (left + chunk_max - 1) / chunk_max;
+      int64_t want = (left + nit - 1) / nit;
       Item it{};
       it.tx = t % p->tiles_x;
       it.ty = t / p->tiles_x;
       it.seg0 = int32_t(segs.size());
-      while (want > 0) {
+      while (want > 0 && int(segs.size()) - it.seg0 < MAX_ITEM_SEGS) {
         const Bin& b = tile_bins[t][bi];
         const int64_t take = std::min(want, b.count - used);
         segs.push_back({int32_t(b.start + used), int32_t(take), b.block, int32_t(items.size())});
         used += take;
         want -= take;
+        left -= take;
         if (used == b.count) {
           ++bi;
           used = 0;
@@ -427,6 +433,7 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   A(dalloc(p, &p->tile_item_off, ntiles + 1));
   A(dalloc(p, &p->bseg_ids, p->n_segs));
   A(dalloc(p, &p->bseg_off_d, p->d + 1));
+  A(dalloc(p, &p->bfac, p->d));
   A(dalloc(p, &p->gscratch, size_t(p->n_items) * (p->T + 7) * (p->T + 7)));
   A(dalloc(p, &p->vis_block, M));
   A(dalloc(p, &p->kbc, KB_TAPS * KB_NC));
@@ -484,6 +491,11 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   up(p->twx, twx.data(), sizeof(float2) * twx.size());
   up(p->twy, twy.data(), sizeof(float2) * twy.size());
   up(p->filt, filt.data(), 4 * filt.size());
+  // default priority on purpose: both streams of an iteration are equal
+  if (st == PPD_OK && (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
+                       hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess))
+    st = fail(PPD_EDEVICE, "creating the second stream failed");
   if (st == PPD_OK && hipDeviceSynchronize() != hipSuccess) st = fail(PPD_EDEVICE, "sync failed");
   if (st != PPD_OK) {
     destroy_plan(p);

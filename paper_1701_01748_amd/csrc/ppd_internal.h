@@ -34,6 +34,7 @@ constexpr int KB_DEG = 9;         // polynomial degree per tap
 constexpr int KB_NC = KB_DEG + 1; // coefficients per tap
 constexpr int N_BASES = 9;        // Dirac + db1..db8
 constexpr int FILT_STRIDE = 16;   // max Daubechies taps (db8)
+constexpr int MAX_ITEM_SEGS = 64; // per-block segments of one work item (one wave scans them)
 constexpr int MAX_XCD = 8;
 
 // A segment: plan-order visibilities [start, start+count) of one data
@@ -69,6 +70,11 @@ struct ppd_plan {
   bool has_theta = false;
   hipStream_t stream = nullptr;
   int device = 0;
+  // second stream of an iteration (the SARA dual step runs there, forked
+  // from and joined back to `stream` through the two events)
+  hipStream_t aux = nullptr;
+  double2* bfac = nullptr;                 // [d] (factor, inside) of the last block_factors call
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // host copies
   std::vector<int64_t> block_off;          // [d+1]
@@ -168,6 +174,9 @@ int grid_plain(ppd_plan* p, const float2* v);                 // v -> grid_a (ac
 int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in);  // dual finish + grid
 
 int plain_dual(ppd_plan* p, const DualArgs& a);               // per-block unfused dual update
+// Per-block projection factors of P_B from per-segment partials of
+// ||q - y||^2: bfac[j] = (min(1, eps_j / r_j), r_j <= eps_j), r_j the block norm.
+int block_factors(ppd_plan* p, const double* part);
 int permute(ppd_plan* p, int direction, const void* in, void* out, int elem_bytes);
 
 int sara_analysis(ppd_plan* p, const float* x, float* coef, const float* W);
@@ -198,22 +207,48 @@ __host__ __device__ inline void kb_weights(float s, const float* __restrict__ c,
   }
 }
 
-// Projection factor of data block j for P_B (Sec. 3.3, eq. proj-L2) from
-// the segment partials of ||q - y_j||^2: inside (r <= eps_j) or eps_j / r.
-// Called by one full wave; fixed summation order, so every workgroup gets
-// the same value.
-__device__ inline void block_factor(int j, const double* __restrict__ part, const int32_t* __restrict__ bids,
-                                    const int32_t* __restrict__ boff, const double* __restrict__ eps,
-                                    double* fac, int* inside) {
-  const int lane = threadIdx.x & 63;
-  double s = 0.0;
-  for (int c = boff[j] + lane; c < boff[j + 1]; c += 64) s += part[bids[c]];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) {
-    const double r = sqrt(s), e = eps[j];
-    *inside = r <= e;
-    *fac = r > e ? e / r : 1.0;
+// Segment table of a work item in LDS: the offsets of its segments in the
+// item's flattened visibility range (pre[n] = total), their first visibility
+// in plan order and their data block.
+struct ItemTab {
+  int pre[MAX_ITEM_SEGS + 1];
+  int start[MAX_ITEM_SEGS];
+  int block[MAX_ITEM_SEGS];
+};
+
+// Wave 0 loads the item's segments (one per lane) and scans their counts;
+// the caller synchronises before use.
+__device__ inline void load_item_tab(const Item& it, const Seg* __restrict__ segs, ItemTab& tab) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int cnt = 0;
+    if (lane < it.seg1 - it.seg0) {
+      const Seg sg = segs[it.seg0 + lane];
+      cnt = sg.count;
+      tab.start[lane] = sg.start;
+      tab.block[lane] = sg.block;
+    }
+    int inc = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(inc, o);
+      if (lane >= o) inc += t;
+    }
+    tab.pre[lane + 1] = inc;
+    if (lane == 0) tab.pre[0] = 0;
   }
+}
+
+// Segment of flattened index li, searching forward from segment s.
+__device__ __forceinline__ int seg_of(int li, int s, const int* pre) {
+  while (li >= pre[s + 1]) ++s;
+  return s;
+}
+
+// Sum over the 64 lanes of a wave by a fixed butterfly (lanes may differ in
+// the last bit; callers use lane 0's value).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
 }
 
 // XCD-aware remap: consecutive workgroup ids go round-robin over the XCDs;

@@ -21,7 +21,8 @@ namespace {
 constexpr int AT = 16;   // analysis output tile per sub-band
 constexpr int ST = 32;   // synthesis output tile (inner levels)
 constexpr int STF = 16;  // synthesis output tile of the last level (8 bases summed)
-constexpr int MAXR = 2 * AT + 2 * FILT_STRIDE;   // staged input extent
+constexpr int SIN = 2 * AT + 2 * FILT_STRIDE - 2;   // staged analysis input extent (db8)
+constexpr int SK = ST / 2 + FILT_STRIDE / 2;         // staged synthesis coefficient extent
 
 struct SaraGeom {
   int nx, ny, L;
@@ -33,176 +34,274 @@ __device__ __host__ inline size_t lvl_size(const SaraGeom& g, int l) { return g.
 
 enum { A_PLAIN = 0, A_DUAL = 1 };
 
+// Filters of db-Q: 2Q taps each, low-pass h and high-pass g, in registers
+// (the addresses are wave-uniform, so the compiler uses scalar loads).
+template <int Q>
+__device__ __forceinline__ void load_filt(const float* __restrict__ filt, float (&h)[2 * Q], float (&g)[2 * Q]) {
+  const float* b = filt + (Q - 1) * 2 * FILT_STRIDE;
+#pragma unroll
+  for (int n = 0; n < 2 * Q; ++n) {
+    h[n] = b[n];
+    g[n] = b[FILT_STRIDE + n];
+  }
+}
+
+// One analysis level of basis db-Q on one output tile: stage the periodic
+// input region, filter the columns (axis 0), then the rows (axis 1).
+// a[k] = sum_n h[n] s[(2k + n) mod L], d[k] likewise with g.
+template <int Q, int MODE>
+__device__ void dwt_tile(const float* __restrict__ src, int sstride, float scale, int hh, int ww, int k0y,
+                         int k0x, int toy, int tox, const float* __restrict__ filt, float* s_in, float* s_lo,
+                         float* s_hi, float* __restrict__ ub, const float* __restrict__ wb, int nx, int oh,
+                         int ow, float* __restrict__ llout, float alpha, float lambda) {
+  constexpr int TAPS = 2 * Q;
+  float h[TAPS], g[TAPS];
+  load_filt<Q>(filt, h, g);
+  // This thread's output position (tiles hold at most blockDim.x outputs):
+  // its weights and, in the dual mode, its u values are loaded before the
+  // input is staged, so both loads are in flight together.
+  const bool mine = int(threadIdx.x) < toy * tox;
+  const int k = mine ? int(threadIdx.x) / tox : 0, m = mine ? int(threadIdx.x) - k * tox : 0;
+  const int r = k0y + k, c = k0x + m;
+  const size_t pos[4] = {size_t(r) * nx + (ow + c), size_t(oh + r) * nx + c, size_t(oh + r) * nx + (ow + c),
+                         size_t(r) * nx + c};
+  const int nout = llout ? 3 : 4;
+  float wv[4] = {1.f, 1.f, 1.f, 1.f}, uo[4] = {0.f, 0.f, 0.f, 0.f};
+  if (mine) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (s < nout) {
+        if (wb) wv[s] = wb[pos[s]];
+        if (MODE == A_DUAL) uo[s] = ub[pos[s]];
+      }
+    }
+  }
+  const int IR = 2 * toy + TAPS - 2, IC = 2 * tox + TAPS - 2;
+  const int ty = threadIdx.x >> 6, tx = threadIdx.x & 63, nty = blockDim.x >> 6;
+  // staging: all of the thread's loads are issued before its LDS stores
+  constexpr int SPT = (SIN + 3) / 4;   // rows per thread with 4 row groups
+  float sv[SPT];
+  const int cx = (2 * k0x + tx) & (ww - 1);
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    const int a = ty + k * nty;
+    if (a < IR && tx < IC) sv[k] = src[size_t((2 * k0y + a) & (hh - 1)) * sstride + cx];
+  }
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    const int a = ty + k * nty;
+    if (a < IR && tx < IC) s_in[a * SIN + tx] = sv[k] * scale;
+  }
+  __syncthreads();
+  for (int kk = ty; kk < toy; kk += nty) {   // columns
+    if (tx < IC) {
+      const float* col = s_in + 2 * kk * SIN + tx;
+      float lo = 0.f, hi = 0.f;
+#pragma unroll
+      for (int n = 0; n < TAPS; ++n) {
+        const float v = col[n * SIN];
+        lo = fmaf(h[n], v, lo);
+        hi = fmaf(g[n], v, hi);
+      }
+      s_lo[kk * SIN + tx] = lo;
+      s_hi[kk * SIN + tx] = hi;
+    }
+  }
+  __syncthreads();
+  if (!mine) return;
+  const float* lrow = s_lo + k * SIN + 2 * m;   // rows
+  const float* hrow = s_hi + k * SIN + 2 * m;
+  float ll = 0.f, lh = 0.f, hl = 0.f, hhv = 0.f;
+#pragma unroll
+  for (int n = 0; n < TAPS; ++n) {
+    const float a = lrow[n], d = hrow[n];
+    ll = fmaf(h[n], a, ll);
+    lh = fmaf(g[n], a, lh);
+    hl = fmaf(h[n], d, hl);
+    hhv = fmaf(g[n], d, hhv);
+  }
+  const float cv[4] = {lh, hl, hhv, ll};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (s >= nout) break;
+    const float cs = cv[s] * wv[s];
+    if (MODE == A_PLAIN) {
+      ub[pos[s]] = cs;
+    } else {
+      // Algorithm 3 steps 19-20 on the coefficient of Psi^H x~
+      const float cl = fminf(fmaxf(uo[s] + cs, -alpha), alpha);
+      ub[pos[s]] = uo[s] + lambda * (cl - uo[s]);
+    }
+  }
+  if (llout) llout[size_t(r) * ow + c] = ll;
+}
+
+static_assert(AT * AT <= 256, "an analysis tile must fit one output per thread of 256");
+
+// Level l of the 8 wavelet bases (blockIdx.z = basis - 1); at level 1 the
+// Dirac basis is blockIdx.z = 8.  Level 1 reads the image scaled by 1/3,
+// deeper levels the low-pass band of the previous level.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float* __restrict__ tmp,
                                              float* __restrict__ out, const float* __restrict__ filt,
                                              const float* __restrict__ W, SaraGeom g, int l, float alpha,
                                              float lambda) {
-  __shared__ float sin_[MAXR * MAXR];
-  __shared__ float slo[AT * MAXR];
-  __shared__ float shi[AT * MAXR];
+  __shared__ float s_in[SIN * SIN];
+  __shared__ float s_lo[AT * SIN];
+  __shared__ float s_hi[AT * SIN];
   const int hh = g.ny >> (l - 1), ww = g.nx >> (l - 1);
   const int oh = hh >> 1, ow = ww >> 1;
   const int toy = min(AT, oh), tox = min(AT, ow);
   const int k0y = blockIdx.y * toy, k0x = blockIdx.x * tox;
-  const int tid = threadIdx.x, nth = blockDim.x;
   const int q = blockIdx.z + 1;   // 1..8 wavelets, 9 = Dirac (level 1 only)
   const float third = 1.0f / 3.0f;
   if (q == 9) {
     // Dirac basis: coefficient x / 3 at every pixel of this tile's footprint
-    for (int i = tid; i < 4 * toy * tox; i += nth) {
-      const int a = i / (2 * tox), b = i - a * (2 * tox);
-      const size_t P = size_t(2 * k0y + a) * g.nx + (2 * k0x + b);
-      const float c = x[P] * third * (W ? W[P] : 1.0f);
-      if (MODE == A_PLAIN) {
-        out[P] = c;
-      } else {
-        const float uo = out[P];
-        const float ub = fminf(fmaxf(uo + c, -alpha), alpha);
-        out[P] = uo + lambda * (ub - uo);
+    // (at most 4 pixels per thread; all loads issued first)
+    constexpr int DPT = 4 * AT * AT / 256;
+    float xv[DPT], wv[DPT], uo[DPT];
+    size_t Pv[DPT];
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+      const int i = threadIdx.x + k * 256;
+      Pv[k] = 0;
+      if (i < 4 * toy * tox) {
+        const int a = i / (2 * tox), b = i - a * (2 * tox);
+        Pv[k] = size_t(2 * k0y + a) * g.nx + (2 * k0x + b);
+        xv[k] = x[Pv[k]];
+        wv[k] = W ? W[Pv[k]] : 1.0f;
+        uo[k] = MODE == A_DUAL ? out[Pv[k]] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+      const int i = threadIdx.x + k * 256;
+      if (i < 4 * toy * tox) {
+        const float c = xv[k] * third * wv[k];
+        if (MODE == A_PLAIN) {
+          out[Pv[k]] = c;
+        } else {
+          const float cl = fminf(fmaxf(uo[k] + c, -alpha), alpha);
+          out[Pv[k]] = uo[k] + lambda * (cl - uo[k]);
+        }
       }
     }
     return;
   }
-  const float* h = filt + (q - 1) * 2 * FILT_STRIDE;
-  const float* gh = h + FILT_STRIDE;
-  const int taps = 2 * q;
-  const int IR = 2 * toy + taps - 2, IC = 2 * tox + taps - 2;
-  // input: level 1 reads the image (scaled by 1/3), deeper levels the
-  // low-pass band of the previous level
-  const float* src;
-  int sstride;
-  float scale;
-  if (l == 1) {
-    src = x;
-    sstride = g.nx;
-    scale = third;
-  } else {
-    src = tmp + g.off[l - 1] + size_t(q - 1) * lvl_size(g, l - 1);
-    sstride = ww;
-    scale = 1.0f;
-  }
-  for (int i = tid; i < IR * IC; i += nth) {
-    const int a = i / IC, b = i - a * IC;
-    const int r = (2 * k0y + a) & (hh - 1), c = (2 * k0x + b) & (ww - 1);
-    sin_[a * IC + b] = src[size_t(r) * sstride + c] * scale;
-  }
-  __syncthreads();
-  for (int i = tid; i < toy * IC; i += nth) {   // columns (axis 0)
-    const int k = i / IC, c = i - k * IC;
-    float lo = 0.f, hi = 0.f;
-    for (int n = 0; n < taps; ++n) {
-      const float s = sin_[(2 * k + n) * IC + c];
-      lo = fmaf(h[n], s, lo);
-      hi = fmaf(gh[n], s, hi);
-    }
-    slo[k * IC + c] = lo;
-    shi[k * IC + c] = hi;
-  }
-  __syncthreads();
+  const float* src = l == 1 ? x : tmp + g.off[l - 1] + size_t(q - 1) * lvl_size(g, l - 1);
+  const int sstride = l == 1 ? g.nx : ww;
+  const float scale = l == 1 ? third : 1.0f;
   float* ub = out + size_t(q) * g.N;
   const float* wb = W ? W + size_t(q) * g.N : nullptr;
-  for (int i = tid; i < toy * tox; i += nth) {  // rows (axis 1)
-    const int k = i / tox, m = i - k * tox;
-    float ll = 0.f, lh = 0.f, hl = 0.f, hh_ = 0.f;
-    for (int n = 0; n < taps; ++n) {
-      const float a = slo[k * IC + 2 * m + n], d = shi[k * IC + 2 * m + n];
-      ll = fmaf(h[n], a, ll);
-      lh = fmaf(gh[n], a, lh);
-      hl = fmaf(h[n], d, hl);
-      hh_ = fmaf(gh[n], d, hh_);
-    }
-    const int r = k0y + k, c = k0x + m;
-    const size_t pLH = size_t(r) * g.nx + (ow + c);
-    const size_t pHL = size_t(oh + r) * g.nx + c;
-    const size_t pHH = size_t(oh + r) * g.nx + (ow + c);
-    const size_t pos[3] = {pLH, pHL, pHH};
-    const float vals[3] = {lh * (wb ? wb[pLH] : 1.0f), hl * (wb ? wb[pHL] : 1.0f), hh_ * (wb ? wb[pHH] : 1.0f)};
-    for (int s = 0; s < 3; ++s) {
-      if (MODE == A_PLAIN) {
-        ub[pos[s]] = vals[s];
-      } else {
-        const float uo = ub[pos[s]];
-        const float cl = fminf(fmaxf(uo + vals[s], -alpha), alpha);
-        ub[pos[s]] = uo + lambda * (cl - uo);
-      }
-    }
-    if (l == g.L) {
-      const size_t pLL = size_t(r) * g.nx + c;
-      if (wb) ll *= wb[pLL];
-      if (MODE == A_PLAIN) {
-        ub[pLL] = ll;
-      } else {
-        const float uo = ub[pLL];
-        const float cl = fminf(fmaxf(uo + ll, -alpha), alpha);
-        ub[pLL] = uo + lambda * (cl - uo);
-      }
-    } else {
-      tmp[g.off[l] + size_t(q - 1) * lvl_size(g, l) + size_t(r) * ow + c] = ll;
-    }
+  float* llout = l == g.L ? nullptr : tmp + g.off[l] + size_t(q - 1) * lvl_size(g, l);
+#define PPD_DWT_CASE(Q)                                                                                     \
+  case Q:                                                                                                   \
+    dwt_tile<Q, MODE>(src, sstride, scale, hh, ww, k0y, k0x, toy, tox, filt, s_in, s_lo, s_hi, ub, wb, g.nx, \
+                      oh, ow, llout, alpha, lambda);                                                        \
+    break;
+  switch (q) {
+    PPD_DWT_CASE(1) PPD_DWT_CASE(2) PPD_DWT_CASE(3) PPD_DWT_CASE(4)
+    PPD_DWT_CASE(5) PPD_DWT_CASE(6) PPD_DWT_CASE(7) PPD_DWT_CASE(8)
   }
+#undef PPD_DWT_CASE
 }
 
-// Inverse of one level for basis q: sub-bands (oh x ow) -> (hh x ww).
-// Writes the tile into `acc` (registers of the caller, indexed by the
-// thread's loop position) through the functor.
-template <typename Sink>
+// Inverse of one level for basis db-Q: sub-bands (oh x ow) -> (hh x ww) on
+// the output tile (y0, x0, tsy x tsx).  Transposing the analysis gives
+// s[2j + e] = sum_t h[2t + e] a[j - t] + g[2t + e] d[j - t], e in {0, 1}, so
+// each thread makes an even / odd output pair from the same Q coefficients.
+// Rows (axis 1) first, then columns (axis 0).  sink(slot, r, c, v) receives
+// the outputs; slot counts the thread's outputs in a fixed order.
+template <int Q, typename Sink>
 __device__ void idwt_tile(const float* __restrict__ llsrc, int llstride, const float* __restrict__ ucoef,
-                          const float* __restrict__ wcoef, const float* __restrict__ llw,
-                          int nx, int hh, int ww, int y0, int x0, int tsy, int tsx,
-                          const float* __restrict__ h, const float* __restrict__ gh, int taps,
+                          const float* __restrict__ wcoef, const float* __restrict__ llw, int nx, int hh,
+                          int ww, int y0, int x0, int tsy, int tsx, const float* __restrict__ filt,
                           float* s_ll, float* s_lh, float* s_hl, float* s_hh, float* s_a, float* s_d,
                           Sink sink) {
+  float h[2 * Q], g[2 * Q];
+  load_filt<Q>(filt, h, g);
   const int tid = threadIdx.x, nth = blockDim.x;
   const int oh = hh >> 1, ow = ww >> 1;
-  const int q = taps >> 1;
-  const int KR = (tsy >> 1) + q, KC = (tsx >> 1) + q;
-  const int krb = (y0 >> 1) - q, kcb = (x0 >> 1) - q;
-  for (int i = tid; i < KR * KC; i += nth) {
-    const int a = i / KC, b = i - a * KC;
-    const int r = (krb + a) & (oh - 1), c = (kcb + b) & (ow - 1);
-    const size_t pll = size_t(r) * llstride + c;
-    const size_t plh = size_t(r) * nx + (ow + c), phl = size_t(oh + r) * nx + c;
-    const size_t phh = size_t(oh + r) * nx + (ow + c);
-    s_ll[i] = llsrc[pll] * (llw ? llw[pll] : 1.0f);
-    s_lh[i] = ucoef[plh] * (wcoef ? wcoef[plh] : 1.0f);
-    s_hl[i] = ucoef[phl] * (wcoef ? wcoef[phl] : 1.0f);
-    s_hh[i] = ucoef[phh] * (wcoef ? wcoef[phh] : 1.0f);
-  }
-  __syncthreads();
-  // rows: A = synth(LL, LH), D = synth(HL, HH) along axis 1
-  for (int i = tid; i < KR * tsx; i += nth) {
-    const int kr = i / tsx, m = i - kr * tsx;
-    const int mp = x0 + m;
-    float av = 0.f, dv = 0.f;
-    for (int n = (mp & 1); n < taps; n += 2) {
-      const int kk = ((mp - n) & (ww - 1)) >> 1;
-      const int lc = (kk - kcb) & (ow - 1);
-      const int li = kr * KC + lc;
-      av = fmaf(h[n], s_ll[li], fmaf(gh[n], s_lh[li], av));
-      dv = fmaf(h[n], s_hl[li], fmaf(gh[n], s_hh[li], dv));
+  const int hx = tsx >> 1, hy = tsy >> 1;
+  const int KR = hy + Q, KC = hx + Q;
+  const int krb = (y0 >> 1) - Q, kcb = (x0 >> 1) - Q;
+  // staging: all of the thread's loads are issued before its LDS stores
+  constexpr int IPT = (SK * SK + 255) / 256;
+  float v4[IPT][4];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const int i = tid + k * nth;
+    if (i < KR * KC) {
+      const int a = i / KC, b = i - a * KC;
+      const int r = (krb + a) & (oh - 1), c = (kcb + b) & (ow - 1);
+      const size_t pll = size_t(r) * llstride + c;
+      const size_t plh = size_t(r) * nx + (ow + c), phl = size_t(oh + r) * nx + c;
+      const size_t phh = size_t(oh + r) * nx + (ow + c);
+      v4[k][0] = llsrc[pll] * (llw ? llw[pll] : 1.0f);
+      v4[k][1] = ucoef[plh] * (wcoef ? wcoef[plh] : 1.0f);
+      v4[k][2] = ucoef[phl] * (wcoef ? wcoef[phl] : 1.0f);
+      v4[k][3] = ucoef[phh] * (wcoef ? wcoef[phh] : 1.0f);
     }
-    s_a[kr * tsx + m] = av;
-    s_d[kr * tsx + m] = dv;
+  }
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const int i = tid + k * nth;
+    if (i < KR * KC) {
+      const int a = i / KC, b = i - a * KC;
+      const int li = a * SK + b;
+      s_ll[li] = v4[k][0];
+      s_lh[li] = v4[k][1];
+      s_hl[li] = v4[k][2];
+      s_hh[li] = v4[k][3];
+    }
   }
   __syncthreads();
-  // columns: S = synth(A, D) along axis 0
+  for (int i = tid; i < KR * hx; i += nth) {   // rows: A from (LL, LH), D from (HL, HH)
+    const int kr = i / hx, j = i - kr * hx;
+    const int base = kr * SK + j + Q;
+    float a0 = 0.f, a1 = 0.f, d0 = 0.f, d1 = 0.f;
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+      const float ll = s_ll[base - t], lh = s_lh[base - t], hl = s_hl[base - t], hv = s_hh[base - t];
+      a0 = fmaf(h[2 * t], ll, fmaf(g[2 * t], lh, a0));
+      a1 = fmaf(h[2 * t + 1], ll, fmaf(g[2 * t + 1], lh, a1));
+      d0 = fmaf(h[2 * t], hl, fmaf(g[2 * t], hv, d0));
+      d1 = fmaf(h[2 * t + 1], hl, fmaf(g[2 * t + 1], hv, d1));
+    }
+    s_a[kr * ST + 2 * j] = a0;
+    s_a[kr * ST + 2 * j + 1] = a1;
+    s_d[kr * ST + 2 * j] = d0;
+    s_d[kr * ST + 2 * j + 1] = d1;
+  }
+  __syncthreads();
   int slot = 0;
-  for (int i = tid; i < tsy * tsx; i += nth, ++slot) {
-    const int m2 = i / tsx, m = i - m2 * tsx;
-    const int mp = y0 + m2;
-    float sv = 0.f;
-    for (int n = (mp & 1); n < taps; n += 2) {
-      const int kk = ((mp - n) & (hh - 1)) >> 1;
-      const int lr = (kk - krb) & (oh - 1);
-      sv = fmaf(h[n], s_a[lr * tsx + m], fmaf(gh[n], s_d[lr * tsx + m], sv));
+  for (int i = tid; i < hy * tsx; i += nth, slot += 2) {   // columns: S from (A, D)
+    const int j = i / tsx, m = i - j * tsx;
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+      const int lr = (j + Q - t) * ST + m;
+      const float av = s_a[lr], dv = s_d[lr];
+      s0 = fmaf(h[2 * t], av, fmaf(g[2 * t], dv, s0));
+      s1 = fmaf(h[2 * t + 1], av, fmaf(g[2 * t + 1], dv, s1));
     }
-    sink(slot, m2, m, sv);
+    sink(slot, 2 * j, m, s0);
+    sink(slot + 1, 2 * j + 1, m, s1);
   }
   __syncthreads();
 }
 
-constexpr int SK = ST / 2 + FILT_STRIDE / 2;   // max staged coefficient extent
+#define PPD_IDWT_SWITCH(q, ...)                       \
+  switch (q) {                                        \
+    case 1: idwt_tile<1>(__VA_ARGS__); break;         \
+    case 2: idwt_tile<2>(__VA_ARGS__); break;         \
+    case 3: idwt_tile<3>(__VA_ARGS__); break;         \
+    case 4: idwt_tile<4>(__VA_ARGS__); break;         \
+    case 5: idwt_tile<5>(__VA_ARGS__); break;         \
+    case 6: idwt_tile<6>(__VA_ARGS__); break;         \
+    case 7: idwt_tile<7>(__VA_ARGS__); break;         \
+    default: idwt_tile<8>(__VA_ARGS__); break;        \
+  }
 
 // Intermediate synthesis level l >= 2 (output = low-pass band of level l-1).
 __global__ __launch_bounds__(256) void k_idwt(const float* __restrict__ u, float* __restrict__ rec,
@@ -214,7 +313,6 @@ __global__ __launch_bounds__(256) void k_idwt(const float* __restrict__ u, float
   const int tsy = min(ST, hh), tsx = min(ST, ww);
   const int y0 = blockIdx.y * tsy, x0 = blockIdx.x * tsx;
   const int q = blockIdx.z + 1;
-  const float* h = filt + (q - 1) * 2 * FILT_STRIDE;
   const float* ucoef = u + size_t(q) * g.N;
   const float* wcoef = W ? W + size_t(q) * g.N : nullptr;
   const float* llsrc;
@@ -228,42 +326,152 @@ __global__ __launch_bounds__(256) void k_idwt(const float* __restrict__ u, float
     llsrc = rec + g.off[l] + size_t(q - 1) * lvl_size(g, l);
   }
   float* dst = rec + g.off[l - 1] + size_t(q - 1) * lvl_size(g, l - 1);
-  idwt_tile(llsrc, llstride, ucoef, wcoef, llw, g.nx, hh, ww, y0, x0, tsy, tsx, h, h + FILT_STRIDE, 2 * q,
-            s_ll, s_lh, s_hl, s_hh, s_a, s_d,
-            [&](int, int r, int c, float v) { dst[size_t(y0 + r) * ww + (x0 + c)] = v; });
+  auto sink = [&](int, int r, int c, float v) { dst[size_t(y0 + r) * ww + (x0 + c)] = v; };
+  PPD_IDWT_SWITCH(q, llsrc, llstride, ucoef, wcoef, llw, g.nx, hh, ww, y0, x0, tsy, tsx, filt, s_ll, s_lh,
+                  s_hl, s_hh, s_a, s_d, sink)
 }
 
-// Level 1 for all 8 wavelet bases, plus the Dirac part, times 1/3.
-__global__ __launch_bounds__(256) void k_idwt_final(const float* __restrict__ u, const float* __restrict__ rec,
-                                                    const float* __restrict__ filt,
-                                                    const float* __restrict__ W, SaraGeom g,
-                                                    float* __restrict__ out) {
-  __shared__ float s_ll[SK * SK], s_lh[SK * SK], s_hl[SK * SK], s_hh[SK * SK];
-  __shared__ float s_a[SK * ST], s_d[SK * ST];
-  const int hh = g.ny, ww = g.nx;
-  const int tsy = min(STF, hh), tsx = min(STF, ww);
-  const int y0 = blockIdx.y * tsy, x0 = blockIdx.x * tsx;
-  float acc[(STF * STF + 255) / 256];
-  for (int s = 0; s < (STF * STF + 255) / 256; ++s) acc[s] = 0.f;
-  for (int q = 1; q <= 8; ++q) {
-    const float* h = filt + (q - 1) * 2 * FILT_STRIDE;
-    const float* ucoef = u + size_t(q) * g.N;
-    const float* wcoef = W ? W + size_t(q) * g.N : nullptr;
-    const float* llsrc = g.L == 1 ? ucoef : rec + g.off[1] + size_t(q - 1) * lvl_size(g, 1);
-    const float* llw = g.L == 1 ? wcoef : nullptr;
-    const int llstride = g.L == 1 ? g.nx : (ww >> 1);
-    idwt_tile(llsrc, llstride, ucoef, wcoef, llw, g.nx, hh, ww, y0, x0, tsy, tsx, h, h + FILT_STRIDE, 2 * q,
-              s_ll, s_lh, s_hl, s_hh, s_a, s_d,
-              [&](int slot, int, int, float v) { acc[slot] += v; });
-  }
-  const float third = 1.0f / 3.0f;
-  int slot = 0;
-  for (int i = threadIdx.x; i < tsy * tsx; i += blockDim.x, ++slot) {
-    const int r = i / tsx, c = i - r * tsx;
-    const size_t P = size_t(y0 + r) * g.nx + (x0 + c);
-    out[P] = (acc[slot] + u[P] * (W ? W[P] : 1.0f)) * third;
+// Level 1 for all 8 wavelet bases, plus the Dirac part, times 1/3, on a
+// STF x STF output tile.  The coefficient windows of all 8 bases are staged
+// in one pass (one round of global loads), then the row passes of all bases,
+// then the column passes, which each thread sums over the bases in registers.
+constexpr int FINAL_THREADS = 128;
+constexpr int FH = STF / 2;                          // coefficients per tile side and band
+constexpr int FKS = FH + FILT_STRIDE / 2;            // staged row stride (FH + max Q)
+constexpr int FROWS = 8 * FH + 36;                   // sum over Q = 1..8 of (FH + Q)
+constexpr int FELEM = 8 * FH * FH + 2 * FH * 36 + 204;   // sum over Q of (FH + Q)^2
+constexpr int FEPT = (FELEM + FINAL_THREADS - 1) / FINAL_THREADS;
+static_assert(FH * STF == FINAL_THREADS, "one column pair per thread");
+
+__device__ __forceinline__ int final_row0(int q) { return (q - 1) * FH + (q - 1) * q / 2; }
+__device__ __forceinline__ int final_elem0(int q) {
+  int e = 0;
+  for (int p = 1; p < q; ++p) e += (FH + p) * (FH + p);
+  return e;
+}
+
+template <int Q>
+__device__ __forceinline__ void final_rows(const float* __restrict__ filt, const float* s_c, float* s_a,
+                                           float* s_d) {
+  float h[2 * Q], g[2 * Q];
+  load_filt<Q>(filt, h, g);
+  constexpr int KR = FH + Q;
+  const int r0 = final_row0(Q);
+  const float* s_ll = s_c;
+  const float* s_lh = s_c + FROWS * FKS;
+  const float* s_hl = s_c + 2 * FROWS * FKS;
+  const float* s_hh = s_c + 3 * FROWS * FKS;
+  for (int i = threadIdx.x; i < KR * FH; i += blockDim.x) {
+    const int kr = i / FH, j = i - kr * FH;
+    const int base = (r0 + kr) * FKS + j + Q;
+    float a0 = 0.f, a1 = 0.f, d0 = 0.f, d1 = 0.f;
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+      const float ll = s_ll[base - t], lh = s_lh[base - t], hl = s_hl[base - t], hv = s_hh[base - t];
+      a0 = fmaf(h[2 * t], ll, fmaf(g[2 * t], lh, a0));
+      a1 = fmaf(h[2 * t + 1], ll, fmaf(g[2 * t + 1], lh, a1));
+      d0 = fmaf(h[2 * t], hl, fmaf(g[2 * t], hv, d0));
+      d1 = fmaf(h[2 * t + 1], hl, fmaf(g[2 * t + 1], hv, d1));
+    }
+    s_a[(r0 + kr) * STF + 2 * j] = a0;
+    s_a[(r0 + kr) * STF + 2 * j + 1] = a1;
+    s_d[(r0 + kr) * STF + 2 * j] = d0;
+    s_d[(r0 + kr) * STF + 2 * j + 1] = d1;
   }
 }
+
+template <int Q>
+__device__ __forceinline__ void final_cols(const float* __restrict__ filt, const float* s_a, const float* s_d,
+                                           int j, int m, float& o0, float& o1) {
+  float h[2 * Q], g[2 * Q];
+  load_filt<Q>(filt, h, g);
+  const int r0 = final_row0(Q);
+#pragma unroll
+  for (int t = 0; t < Q; ++t) {
+    const int lr = (r0 + j + Q - t) * STF + m;
+    const float av = s_a[lr], dv = s_d[lr];
+    o0 = fmaf(h[2 * t], av, fmaf(g[2 * t], dv, o0));
+    o1 = fmaf(h[2 * t + 1], av, fmaf(g[2 * t + 1], dv, o1));
+  }
+}
+
+__global__ __launch_bounds__(FINAL_THREADS) void k_idwt_final(const float* __restrict__ u,
+                                                              const float* __restrict__ rec,
+                                                              const float* __restrict__ filt,
+                                                              const float* __restrict__ W, SaraGeom g,
+                                                              float* __restrict__ out) {
+  __shared__ float s_c[4 * FROWS * FKS];
+  __shared__ float s_a[FROWS * STF], s_d[FROWS * STF];
+  const int nx = g.nx, ww = g.nx, hh = g.ny;
+  const int oh = hh >> 1, ow = ww >> 1;
+  const int y0 = blockIdx.y * STF, x0 = blockIdx.x * STF;
+  const int tid = threadIdx.x;
+  // stage: element e of the flattened (basis, row, column) windows
+  float vals[FEPT][4];
+  int at[FEPT];
+#pragma unroll
+  for (int k = 0; k < FEPT; ++k) {
+    const int e = tid + k * FINAL_THREADS;
+    at[k] = -1;
+    if (e < FELEM) {
+      int q = 1;
+#pragma unroll
+      for (int p = 2; p <= 8; ++p)
+        if (e >= final_elem0(p)) q = p;
+      const int KC = FH + q;
+      const int le = e - final_elem0(q);
+      const int a = le / KC, b = le - a * KC;
+      const int r = ((y0 >> 1) - q + a) & (oh - 1), c = ((x0 >> 1) - q + b) & (ow - 1);
+      const float* ucoef = u + size_t(q) * g.N;
+      const float* wcoef = W ? W + size_t(q) * g.N : nullptr;
+      const size_t plh = size_t(r) * nx + (ow + c), phl = size_t(oh + r) * nx + c;
+      const size_t phh = size_t(oh + r) * nx + (ow + c);
+      if (g.L == 1) {
+        const size_t pll = size_t(r) * nx + c;
+        vals[k][0] = ucoef[pll] * (wcoef ? wcoef[pll] : 1.0f);
+      } else {
+        vals[k][0] = rec[g.off[1] + size_t(q - 1) * lvl_size(g, 1) + size_t(r) * ow + c];
+      }
+      vals[k][1] = ucoef[plh] * (wcoef ? wcoef[plh] : 1.0f);
+      vals[k][2] = ucoef[phl] * (wcoef ? wcoef[phl] : 1.0f);
+      vals[k][3] = ucoef[phh] * (wcoef ? wcoef[phh] : 1.0f);
+      at[k] = (final_row0(q) + a) * FKS + b;
+    }
+  }
+  const int j = tid / STF, m = tid - j * STF;
+  const size_t P0 = size_t(y0 + 2 * j) * nx + (x0 + m), P1 = P0 + nx;
+  const float dirac0 = u[P0] * (W ? W[P0] : 1.0f), dirac1 = u[P1] * (W ? W[P1] : 1.0f);
+#pragma unroll
+  for (int k = 0; k < FEPT; ++k) {
+    if (at[k] >= 0) {
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) s_c[c4 * FROWS * FKS + at[k]] = vals[k][c4];
+    }
+  }
+  __syncthreads();
+  final_rows<1>(filt, s_c, s_a, s_d);
+  final_rows<2>(filt, s_c, s_a, s_d);
+  final_rows<3>(filt, s_c, s_a, s_d);
+  final_rows<4>(filt, s_c, s_a, s_d);
+  final_rows<5>(filt, s_c, s_a, s_d);
+  final_rows<6>(filt, s_c, s_a, s_d);
+  final_rows<7>(filt, s_c, s_a, s_d);
+  final_rows<8>(filt, s_c, s_a, s_d);
+  __syncthreads();
+  float o0 = 0.f, o1 = 0.f;
+  final_cols<1>(filt, s_a, s_d, j, m, o0, o1);
+  final_cols<2>(filt, s_a, s_d, j, m, o0, o1);
+  final_cols<3>(filt, s_a, s_d, j, m, o0, o1);
+  final_cols<4>(filt, s_a, s_d, j, m, o0, o1);
+  final_cols<5>(filt, s_a, s_d, j, m, o0, o1);
+  final_cols<6>(filt, s_a, s_d, j, m, o0, o1);
+  final_cols<7>(filt, s_a, s_d, j, m, o0, o1);
+  final_cols<8>(filt, s_a, s_d, j, m, o0, o1);
+  const float third = 1.0f / 3.0f;
+  out[P0] = (o0 + dirac0) * third;
+  out[P1] = (o1 + dirac1) * third;
+}
+#undef PPD_IDWT_SWITCH
 
 // Algorithm 1 weights (eq. reweighting): W = omega / (omega + |c|), in
 // place over the analysis coefficients c.
@@ -329,10 +537,9 @@ int sara_synthesis(ppd_plan* p, const float* u, float* out, const float* W) {
     PPD_HIP(hipGetLastError());
     PPD_TRY(timer_end(p, slot));
   }
-  const int tsy = std::min(STF, g.ny), tsx = std::min(STF, g.nx);
   int slot;
   PPD_TRY(timer_begin(p, KK_IDWT, &slot));
-  hipLaunchKernelGGL(k_idwt_final, dim3(g.nx / tsx, g.ny / tsy), dim3(256), 0, p->stream, u, p->sara_rec,
+  hipLaunchKernelGGL(k_idwt_final, dim3(g.nx / STF, g.ny / STF), dim3(FINAL_THREADS), 0, p->stream, u, p->sara_rec,
                      p->filt, W, g, out);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
