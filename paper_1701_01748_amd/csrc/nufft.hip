@@ -201,14 +201,23 @@ __global__ __launch_bounds__(64 * DEGRID_WAVES) void k_degrid(
   }
 }
 
-// Gridding workgroup shape: NW waves, each owning two private copies (A, B)
-// of the (T+7)^2 region in LDS.  Even visibilities of a batch go to copy A,
-// odd ones to copy B: two independent read-modify-write chains per wave
-// that the compiler may interleave (distinct LDS arrays cannot alias).
+// Gridding workgroup shape: NW waves, each owning C private copies of the
+// (T+7)^2 region in LDS (rows padded to T+8 cells, so the 8 tap rows of a
+// footprint fall in distinct LDS banks).  Visibility k of a batch goes to
+// copy k mod C: C independent read-modify-write chains per wave that the
+// compiler interleaves (distinct LDS arrays cannot alias).
+#ifndef PPD_GRID_CHAINS
+#define PPD_GRID_CHAINS 2
+#endif
+#ifndef PPD_GRID_WAVES16
+#define PPD_GRID_WAVES16 2
+#endif
 template <int T>
 struct GridCfg {
   static constexpr int R = T + 7;
-  static constexpr int NW = (T <= 16) ? 4 : (T <= 32 ? 2 : 1);
+  static constexpr int RS = T + 8;
+  static constexpr int C = (T <= 32) ? PPD_GRID_CHAINS : 2;
+  static constexpr int NW = (T <= 16) ? PPD_GRID_WAVES16 : (T <= 32 ? 2 : 1);
   static constexpr int THREADS = NW * 64;
 };
 
@@ -221,9 +230,10 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     float2* __restrict__ v, double2* __restrict__ z, const double2* __restrict__ w, double mu,
     double lambda, const double2* __restrict__ bfac) {
   constexpr int R = GridCfg<T>::R;
+  constexpr int RS = GridCfg<T>::RS;
+  constexpr int C = GridCfg<T>::C;
   constexpr int NW = GridCfg<T>::NW;
-  __shared__ float2 acc_a[NW][R * R];
-  __shared__ float2 acc_b[NW][R * R];
+  __shared__ float2 acc[NW][C][R * RS];
   constexpr int WXS = KB_TAPS + 1;             // staging stride per visibility (bank spread)
   __shared__ float2 wxv[NW][64 * WXS];         // wx[b] * value, per visibility of the batch
   __shared__ float wyb[NW][64 * WXS];          // wy[a]
@@ -236,18 +246,14 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int uwid = __builtin_amdgcn_readfirstlane(wid);   // wave-uniform
   load_item_tab(it, segs, tab);
-  for (int i = threadIdx.x; i < NW * R * R; i += blockDim.x) {
-    (&acc_a[0][0])[i] = make_float2(0.f, 0.f);
-    (&acc_b[0][0])[i] = make_float2(0.f, 0.f);
-  }
+  for (int i = threadIdx.x; i < NW * C * R * RS; i += blockDim.x) (&acc[0][0][0])[i] = make_float2(0.f, 0.f);
   for (int i = threadIdx.x; i < KB_TAPS * KB_NC; i += blockDim.x) coef[i] = kbc[i];
   __syncthreads();
-  float2* accA = acc_a[wid];
-  float2* accB = acc_b[wid];
+  float2 (*myacc)[R * RS] = acc[wid];
   float2* mywxv = wxv[wid];
   float* mywy = wyb[wid];
   const int ta = lane >> 3, tb = lane & 7;   // tap of this lane in the apply phase
-  const int lofs = ta * R + tb;
+  const int lofs = ta * RS + tb;
   // The item's visibilities (all segments, flattened) are taken in batches
   // of 64, batch k by wave k mod NW.  The global operands of a wave's next
   // batch are loaded before its current batch is prepared and applied, so
@@ -321,7 +327,7 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
       }
       vx = val.x * bt.th;
       vy = val.y * bt.th;
-      pos = t.ov * R + t.ou;
+      pos = t.ov * RS + t.ou;
     } else {
 #pragma unroll
       for (int m = 0; m < KB_TAPS; ++m) {
@@ -338,23 +344,28 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     // apply: lane (a, b) owns tap (a, b) of one visibility at a time, so
     // the wave's 64 read-modify-writes touch distinct cells (LDS float
     // atomics are far slower on this part, collisions or not).
-    // Two visibilities per step, even ones into copy A and odd ones into
-    // copy B: two independent read-modify-write chains.  (Register
-    // accumulation over visibilities sharing a cell was measured slower.)
-    const int nb2 = (nb + 1) & ~1;
-    for (int k = 0; k < nb2; k += 2) {
-      const int pa = __builtin_amdgcn_readlane(pos, k) + lofs;
-      const int pb = __builtin_amdgcn_readlane(pos, k + 1) + lofs;
-      const float2 xa = mywxv[k * WXS + tb], xb = mywxv[(k + 1) * WXS + tb];
-      const float ga = mywy[k * WXS + ta], gb = mywy[(k + 1) * WXS + ta];
-      float2 ca = accA[pa];
-      float2 cb = accB[pb];
-      ca.x = fmaf(ga, xa.x, ca.x);
-      ca.y = fmaf(ga, xa.y, ca.y);
-      cb.x = fmaf(gb, xb.x, cb.x);
-      cb.y = fmaf(gb, xb.y, cb.y);
-      accA[pa] = ca;
-      accB[pb] = cb;
+    // C visibilities per step, visibility k into copy k mod C: C independent
+    // read-modify-write chains.  (Summing runs of visibilities that share a
+    // first-tap cell in registers before one read-modify-write per run was
+    // measured slower: the data-dependent loop costs more than it saves.)
+    const int nbc = (nb + C - 1) / C * C;
+    for (int k = 0; k < nbc; k += C) {
+      int pc[C];
+      float2 xc[C], cc[C];
+      float gc[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        pc[j] = __builtin_amdgcn_readlane(pos, k + j) + lofs;
+        xc[j] = mywxv[(k + j) * WXS + tb];
+        gc[j] = mywy[(k + j) * WXS + ta];
+        cc[j] = myacc[j][pc[j]];
+      }
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        cc[j].x = fmaf(gc[j], xc[j].x, cc[j].x);
+        cc[j].y = fmaf(gc[j], xc[j].y, cc[j].y);
+        myacc[j][pc[j]] = cc[j];
+      }
     }
     __builtin_amdgcn_wave_barrier();
     if (DUAL && lane < nb) {
@@ -365,12 +376,15 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
   __syncthreads();
   float2* dst = scratch + size_t(ii) * (R * R);
   for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
+    const int ra = i / R, li = ra * RS + (i - ra * R);
     float sx = 0.f, sy = 0.f;
 #pragma unroll
-    for (int q2 = 0; q2 < NW; ++q2) {
-      sx += acc_a[q2][i].x + acc_b[q2][i].x;
-      sy += acc_a[q2][i].y + acc_b[q2][i].y;
-    }
+    for (int q2 = 0; q2 < NW; ++q2)
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        sx += acc[q2][j][li].x;
+        sy += acc[q2][j][li].y;
+      }
     dst[i] = make_float2(sx, sy);
   }
 }

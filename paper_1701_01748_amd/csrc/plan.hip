@@ -55,7 +55,9 @@ double kb_ft(double xi, double beta) {
 // Tap m of a visibility with fractional grid offset s in [0, 1) sits at
 // distance s + 3 - m from the kernel centre.  Each tap is interpolated by a
 // degree-9 polynomial in x = 2s - 1 through 10 Chebyshev nodes (solved in
-// float64 by Gaussian elimination with partial pivoting).
+// float64 by Gaussian elimination with partial pivoting).  The nodes are
+// symmetric in x, so tap 7-m's polynomial is tap m's at -x; the device
+// evaluation reads taps 0..3 only.
 void kb_tap_polynomials(double beta, float* coef) {
   const int n = KB_NC;
   for (int m = 0; m < KB_TAPS; ++m) {

@@ -196,16 +196,29 @@ void daubechies(int p, double* h);
 // ---- device helpers --------------------------------------------------------
 namespace ppd {
 
+// The 8 tap weights at fractional offset s in [0, 1), x = 2s - 1.  The
+// kernel is even, so tap 7-m at x equals tap m at -x: with the even and odd
+// parts of tap m's polynomial, P(+-x) = E(x^2) +- x O(x^2), four polynomial
+// pairs give all eight weights (half the multiply-adds of eight Horner
+// evaluations).  c holds the coefficients of taps 0..3 (of 8) in powers of x.
 __host__ __device__ inline void kb_weights(float s, const float* __restrict__ c, float* w) {
   const float x = 2.0f * s - 1.0f;
+  const float y = x * x;
 #pragma unroll
-  for (int m = 0; m < KB_TAPS; ++m) {
-    float acc = c[m * KB_NC + KB_DEG];
+  for (int m = 0; m < KB_TAPS / 2; ++m) {
+    const float* cm = c + m * KB_NC;
+    float e = cm[KB_DEG - 1], o = cm[KB_DEG];   // KB_DEG is odd
 #pragma unroll
-    for (int k = KB_DEG - 1; k >= 0; --k) acc = fmaf(acc, x, c[m * KB_NC + k]);
-    w[m] = acc;
+    for (int k = KB_DEG - 3; k >= 0; k -= 2) {
+      e = fmaf(e, y, cm[k]);
+      o = fmaf(o, y, cm[k + 1]);
+    }
+    const float xo = x * o;
+    w[m] = e + xo;
+    w[KB_TAPS - 1 - m] = e - xo;
   }
 }
+static_assert(KB_DEG % 2 == 1, "even / odd split assumes an odd degree");
 
 // Segment table of a work item in LDS: the offsets of its segments in the
 // item's flattened visibility range (pre[n] = total), their first visibility
