@@ -147,6 +147,19 @@ int ppd_reweight(ppd_plan* plan, const float* x, float omega, float* W);
 int ppd_ellipsoid_proj(ppd_plan* plan, const double* w, const float* y, const double* U,
                        const double* eps, int n_itr, double mu, double* zbar_inout);
 
+/* The prox of eq. elip-proj-1 itself (the exact alternative the paper
+ * names next to Algorithm 2, Sec. 4.1): per block j,
+ *     z = argmin_{||z - y_j|| <= eps_j} (w - z)^H U_j (w - z) / 2
+ *       = (U w + nu_j y) / (U + nu_j),
+ * nu_j = 0 if ||w - y_j|| <= eps_j, else the root of ||U (w - y_j) / (U + nu)||
+ * = eps_j, found by n_newton Newton steps on 1 / ||.|| - 1 / eps_j from
+ * nu = 0 (concave and increasing in nu, so the steps approach the root
+ * monotonically from below).  FP64.  w, z: [M] complex128 (z may alias
+ * nothing else); y: [M] complex64; U: [M] float64 > 0; eps: HOST [d];
+ * nu: optional DEVICE [d] float64 output.  1 <= n_newton <= 64.  Plan order. */
+int ppd_prox_metric(ppd_plan* plan, const double* w, const float* y, const double* U,
+                    const double* eps, int n_newton, double* z, double* nu);
+
 /* ---- setup quantities (Sec. 4.3, Sec. 5.1) ------------------------------ */
 /* Uniform-weighting preconditioner: the inverse sampling density near each
  * visibility.  Points are counted on an ny x nx u-v cell grid, cell
@@ -176,6 +189,10 @@ typedef struct {
 #define PPD_FORM_PLAIN 1   /* unfused reference form: Phi, per-block FP64
                               dual kernels, Phi^H, each a separate launch     */
 
+#define PPD_PROX_FB    0   /* prox^U_h by n_itr Algorithm 2 iterations        */
+#define PPD_PROX_EXACT 1   /* prox^U_h exactly (ppd_prox_metric, n_newton
+                              Newton steps); fused form only                  */
+
 typedef struct {
   double tau, eta, zeta, lambda;   /* Algorithm 3 step sizes and relaxation   */
   double alpha;                    /* l1 dual clip kappa ||Psi W||_S^2        */
@@ -190,6 +207,8 @@ typedef struct {
   const float* x_true;             /* optional [ny][nx] reference for SNR     */
   const float* W;                  /* optional [9][ny][nx] re-weights (Algorithm 1),
                                       NULL = identity                          */
+  int32_t prox;                    /* PPD_PROX_* (0 = Algorithm 2)            */
+  int32_t n_newton;                /* Newton steps for PPD_PROX_EXACT (0 -> 12) */
 } ppd_params;
 
 typedef struct {
@@ -204,7 +223,9 @@ typedef struct {
  * basis is updated each iteration) on `state`.  Step 10 is read as
  * vbar_j = U_j (w_j - prox^U_h(w_j)), w_j = U_j^{-1} v_j + Theta_j G_j a,
  * with the prox approximated by n_itr Algorithm 2 iterations warm-started
- * from state->z.  W_i = params->W (identity if NULL).  If stats (HOST) is
+ * from state->z (PPD_PROX_FB), or computed as by ppd_prox_metric
+ * (PPD_PROX_EXACT; state->z then holds the last prox).  W_i = params->W
+ * (identity if NULL).  If stats (HOST) is
  * non-NULL the call synchronises and fills it (and residual[d], HOST, if
  * non-NULL) from FP64 reductions of the last iteration. */
 int ppd_iterate(ppd_plan* plan, ppd_state* state, const ppd_params* params, int n_iter,

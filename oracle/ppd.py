@@ -60,6 +60,7 @@ class Params:
     mu: float = 1.0         # Algorithm 2 step, 1 / max(U)
     n_itr: int = 1          # Algorithm 2 iterations per outer iteration
     levels: int = 3
+    prox: str = "fb"        # "fb": Algorithm 2 (n_itr steps); "exact": prox^U_h itself
 
 
 def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
@@ -90,8 +91,13 @@ def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
             s = slice(int(block_off[j]), int(block_off[j + 1]))
             res.append(np.linalg.norm(Ga[s] - y[s]))
             w = state.v[s] / U[s] + Ga[s]
-            z = prox.fb_ellipsoid(w, y[s], eps[j], U[s], p.mu, p.n_itr, state.z[s])
-            if trace is not None:
+            if p.prox == "exact":                          # eq. elip-proj-1 solved exactly
+                z = prox.prox_metric_exact(w, y[s], eps[j], U[s])
+            else:
+                z = prox.fb_ellipsoid(w, y[s], eps[j], U[s], p.mu, p.n_itr, state.z[s])
+            if trace is not None and p.prox == "exact":
+                sets_proj.append((bool(np.linalg.norm(w - y[s]) > eps[j]),))
+            elif trace is not None:
                 zz, proj = state.z[s], []
                 for _ in range(p.n_itr):
                     q = zz - p.mu * U[s] * (zz - w)

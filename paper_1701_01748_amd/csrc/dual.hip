@@ -122,6 +122,142 @@ __global__ __launch_bounds__(256) void k_block_factors(const double* __restrict_
   }
 }
 
+// ---- exact prox of eq. elip-proj-1: Newton on the secular equation ------
+// With a = U |w - y| and r(nu)^2 = sum a^2 / (U + nu)^2 per block, the prox
+// is (U w + nu y) / (U + nu) at the root of g(nu) = 1 / r(nu) - 1 / eps
+// (nu = 0 when r(0) <= eps).  g is concave and increasing, so Newton from
+// nu = 0 climbs to the root without overshooting; g'(nu) = S3 / r^3 with
+// S3 = sum a^2 / (U + nu)^3.  bfac[j].x carries nu between the passes.
+
+// Per-segment partials S2, S3 at the block's current nu (0 on the first pass).
+constexpr int SEC_WAVES = 4;
+__global__ __launch_bounds__(64 * SEC_WAVES) void k_sec_partials(
+    const Item* __restrict__ items, int n_items, const Seg* __restrict__ segs, const double2* __restrict__ w,
+    const float2* __restrict__ y, const double* __restrict__ U, const double2* __restrict__ bfac, int first,
+    double* __restrict__ p2, double* __restrict__ p3) {
+  constexpr int NW = SEC_WAVES;
+  __shared__ ItemTab tab;
+  __shared__ double s2[NW][MAX_ITEM_SEGS], s3[NW][MAX_ITEM_SEGS];
+  const int ii = xcd_remap(blockIdx.x, gridDim.x);
+  if (ii >= n_items) return;
+  const Item it = items[ii];
+  const int lane = threadIdx.x & 63;
+  const int uwid = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  load_item_tab(it, segs, tab);
+  for (int i = threadIdx.x; i < NW * MAX_ITEM_SEGS; i += blockDim.x) {
+    (&s2[0][0])[i] = 0.0;
+    (&s3[0][0])[i] = 0.0;
+  }
+  __syncthreads();
+  const int nseg = it.seg1 - it.seg0;
+  const int total = tab.pre[nseg];
+  int sb = 0;
+  for (int bt = uwid; bt * 64 < total; bt += NW) {
+    while (bt * 64 >= tab.pre[sb + 1]) ++sb;
+    const int li = bt * 64 + lane;
+    const bool act = li < total;
+    const int sg = act ? seg_of(li, sb, tab.pre) : sb;
+    double t2 = 0.0, t3 = 0.0;
+    if (act) {
+      const int pi = tab.start[sg] + (li - tab.pre[sg]);
+      const double2 we = w[pi];
+      const float2 ye = y[pi];
+      const double Ue = U[pi];
+      const double nu = first ? 0.0 : bfac[tab.block[sg]].x;
+      const double dx = we.x - double(ye.x), dy = we.y - double(ye.y);
+      const double a2 = Ue * Ue * (dx * dx + dy * dy);
+      const double inv = 1.0 / (Ue + nu);
+      t2 = a2 * inv * inv;
+      t3 = t2 * inv;
+    }
+    const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
+    for (int ss = sb; ss <= slast; ++ss) {
+      const double a = wave_sum(act && sg == ss ? t2 : 0.0);
+      const double b = wave_sum(act && sg == ss ? t3 : 0.0);
+      if (lane == 0) {
+        s2[uwid][ss] += a;
+        s3[uwid][ss] += b;
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nseg; k += blockDim.x) {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < NW; ++wv) {
+      a += s2[wv][k];
+      b += s3[wv][k];
+    }
+    p2[it.seg0 + k] = a;
+    p3[it.seg0 + k] = b;
+  }
+}
+
+// One Newton step per block: workgroup j sums the segment partials in a
+// fixed order and updates nu_j = max(0, nu_j - g / g').
+__global__ __launch_bounds__(256) void k_sec_update(const double* __restrict__ p2, const double* __restrict__ p3,
+                                                    const int32_t* __restrict__ bids,
+                                                    const int32_t* __restrict__ boff,
+                                                    const double* __restrict__ eps, int first,
+                                                    double2* __restrict__ bfac) {
+  __shared__ double red2[4], red3[4];
+  const int j = blockIdx.x;
+  const int c0 = boff[j], c1 = boff[j + 1];
+  double a = 0.0, b = 0.0;
+  for (int base = c0; base < c1; base += 256 * BF_PER) {
+    int id[BF_PER];
+#pragma unroll
+    for (int k = 0; k < BF_PER; ++k) {
+      const int c = base + int(threadIdx.x) + k * 256;
+      id[k] = c < c1 ? bids[c] : -1;
+    }
+    double va[BF_PER], vb[BF_PER];
+#pragma unroll
+    for (int k = 0; k < BF_PER; ++k) {
+      va[k] = id[k] >= 0 ? p2[id[k]] : 0.0;
+      vb[k] = id[k] >= 0 ? p3[id[k]] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < BF_PER; ++k) {
+      a += va[k];
+      b += vb[k];
+    }
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    red2[threadIdx.x >> 6] = a;
+    red3[threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double S2 = (red2[0] + red2[1]) + (red2[2] + red2[3]);
+    const double S3 = (red3[0] + red3[1]) + (red3[2] + red3[3]);
+    const double nu0 = first ? 0.0 : bfac[j].x;
+    double nu = 0.0;
+    if (S2 > 0.0 && S3 > 0.0) {
+      const double r = sqrt(S2), e = eps[j];
+      const double g = 1.0 / r - 1.0 / e, gp = S3 / (r * r * r);
+      nu = fmax(0.0, nu0 - g / gp);
+    }
+    bfac[j] = make_double2(nu, 0.0);
+  }
+}
+
+// z = (U w + nu y) / (U + nu) with the block's nu (z = w when nu = 0).
+__global__ void k_prox_apply(int64_t M, const int32_t* __restrict__ vblk, const double2* __restrict__ w,
+                             const float2* __restrict__ y, const double* __restrict__ U,
+                             const double2* __restrict__ bfac, double2* __restrict__ z) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < M; i += int64_t(gridDim.x) * blockDim.x) {
+    const double nu = bfac[vblk[i]].x, Ue = U[i];
+    const double2 we = w[i];
+    const float2 ye = y[i];
+    const double inv = 1.0 / (Ue + nu);
+    z[i] = nu == 0.0 ? we   // inside the ellipsoid: the prox is w itself
+                     : make_double2((Ue * we.x + nu * double(ye.x)) * inv, (Ue * we.y + nu * double(ye.y)) * inv);
+  }
+}
+
 // ---- plain form: one block at a time, each step its own launch ---------
 constexpr int PL_THREADS = 256;
 constexpr int PL_MAX_BLOCKS = 512;
@@ -259,6 +395,25 @@ int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* y, const 
   return timer_end(p, slot);
 }
 
+int secular_solve(ppd_plan* p, const double2* w, const float2* y, const double* U, int n_newton) {
+  double* p2 = p->part;
+  double* p3 = p->part + p->n_segs;
+  for (int s = 0; s < n_newton; ++s) {
+    int slot;
+    PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
+    hipLaunchKernelGGL(k_sec_partials, dim3(p->n_launch), dim3(64 * SEC_WAVES), 0, p->stream, p->items,
+                       p->n_items, p->segs, w, y, U, p->bfac, int(s == 0), p2, p3);
+    PPD_HIP(hipGetLastError());
+    PPD_TRY(timer_end(p, slot));
+    PPD_TRY(timer_begin(p, KK_MISC, &slot));
+    hipLaunchKernelGGL(k_sec_update, dim3(p->d), dim3(256), 0, p->stream, p2, p3, p->bseg_ids, p->bseg_off_d,
+                       p->eps_d, int(s == 0), p->bfac);
+    PPD_HIP(hipGetLastError());
+    PPD_TRY(timer_end(p, slot));
+  }
+  return PPD_OK;
+}
+
 int block_factors(ppd_plan* p, const double* part) {
   int slot;
   PPD_TRY(timer_begin(p, KK_MISC, &slot));
@@ -315,6 +470,27 @@ extern "C" int ppd_ellipsoid_proj(ppd_plan* p, const double* w, const float* y, 
     std::swap(pa, pb);
   }
   return alg2_launch(p, 2, w2, y2, U, z2, mu, pa, nullptr);
+}
+
+extern "C" int ppd_prox_metric(ppd_plan* p, const double* w, const float* y, const double* U, const double* eps,
+                               int n_newton, double* z, double* nu) {
+  if (!p || !w || !y || !U || !eps || !z) return fail(PPD_EINVAL, "ppd_prox_metric: NULL argument");
+  if (n_newton < 1 || n_newton > 64) return fail(PPD_EINVAL, "ppd_prox_metric: n_newton must be in [1, 64]");
+  PPD_TRY(upload_eps(p, eps));
+  const double2* w2 = reinterpret_cast<const double2*>(w);
+  const float2* y2 = reinterpret_cast<const float2*>(y);
+  PPD_TRY(secular_solve(p, w2, y2, U, n_newton));
+  int slot;
+  PPD_TRY(timer_begin(p, KK_MISC, &slot));
+  hipLaunchKernelGGL(k_prox_apply, dim3(int(std::min<int64_t>((p->M + 255) / 256, 4096))), dim3(256), 0, p->stream,
+                     p->M, p->vis_block, w2, y2, U, p->bfac, reinterpret_cast<double2*>(z));
+  PPD_HIP(hipGetLastError());
+  PPD_TRY(timer_end(p, slot));
+  if (nu) {
+    PPD_HIP(hipMemcpy2DAsync(nu, sizeof(double), p->bfac, sizeof(double2), sizeof(double), p->d,
+                             hipMemcpyDeviceToDevice, p->stream));
+  }
+  return PPD_OK;
 }
 
 extern "C" int ppd_uniform_weights(ppd_plan* p, double* U) {

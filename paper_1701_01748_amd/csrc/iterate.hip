@@ -120,6 +120,7 @@ struct IterCtx {
   const float* W;
   float alpha, lambda;
   int form;
+  int prox, n_newton;
 };
 
 // Runs the plan's launches on another stream for the lifetime of the object.
@@ -146,7 +147,11 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
     PPD_HIP(hipEventRecord(p->ev_join, p->aux));
   }
   PPD_TRY(fft_forward(p, xt));                              // step 4: a = F Z x~
-  if (c.form == PPD_FORM_FUSED) {
+  if (c.form == PPD_FORM_FUSED && c.prox == PPD_PROX_EXACT) {
+    PPD_TRY(degrid_dual(p, c.dual, p->part));               // step 10 argument w
+    PPD_TRY(secular_solve(p, p->wbuf, c.dual.y, c.dual.U, c.n_newton));   // exact prox^U_h(w)
+    PPD_TRY(grid_dual_exact(p, c.dual));                    // steps 10-12
+  } else if (c.form == PPD_FORM_FUSED) {
     double* pa = p->part;
     double* pb = p->part + p->n_segs;
     PPD_TRY(degrid_dual(p, c.dual, pa));                    // step 10 argument, first Alg. 2 step
@@ -167,11 +172,11 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
 
 std::string graph_key(const IterCtx& c) {
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d",
+  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d %d %d",
                 (void*)c.dual.y, (void*)c.dual.U, (void*)c.dual.v, (void*)c.dual.z, (void*)c.primal.x,
                 (void*)c.primal.xt, (void*)c.primal.x_true, (void*)c.u, (void*)c.primal.ut, (void*)c.W, c.dual.mu,
                 c.dual.lambda, c.primal.tau, c.primal.eta, c.primal.zeta, double(c.alpha),
-                double(c.lambda), c.dual.n_itr, c.form);
+                double(c.lambda), c.dual.n_itr, c.form, c.prox, c.n_newton);
   return std::string(buf);
 }
 
@@ -200,6 +205,11 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   if (prm->n_itr < 1) return fail(PPD_EINVAL, "ppd_iterate: n_itr must be >= 1");
   if (prm->form != PPD_FORM_FUSED && prm->form != PPD_FORM_PLAIN)
     return fail(PPD_EINVAL, "ppd_iterate: unknown form");
+  if (prm->prox != PPD_PROX_FB && prm->prox != PPD_PROX_EXACT)
+    return fail(PPD_EINVAL, "ppd_iterate: unknown prox");
+  if (prm->prox == PPD_PROX_EXACT && prm->form != PPD_FORM_FUSED)
+    return fail(PPD_EUNSUPPORTED, "ppd_iterate: the exact prox is implemented in the fused form only");
+  if (prm->n_newton < 0 || prm->n_newton > 64) return fail(PPD_EINVAL, "ppd_iterate: n_newton must be in [0, 64]");
   const double vals[6] = {prm->tau, prm->eta, prm->zeta, prm->lambda, prm->alpha, prm->mu};
   for (double v : vals)
     if (!std::isfinite(v)) return fail(PPD_EINVAL, "ppd_iterate: non-finite parameter");
@@ -232,6 +242,8 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   c.alpha = float(prm->alpha);
   c.lambda = float(prm->lambda);
   c.form = prm->form;
+  c.prox = prm->prox;
+  c.n_newton = prm->n_newton == 0 ? 12 : prm->n_newton;
 
   if (n_iter > 0) {
     if (prm->use_graph) {

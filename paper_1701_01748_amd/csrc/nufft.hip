@@ -228,7 +228,7 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
     const float2* __restrict__ vin, const float2* __restrict__ y, const double* __restrict__ U,
     float2* __restrict__ v, double2* __restrict__ z, const double2* __restrict__ w, double mu,
-    double lambda, const double2* __restrict__ bfac) {
+    double lambda, const double2* __restrict__ bfac, int exact) {
   constexpr int R = GridCfg<T>::R;
   constexpr int RS = GridCfg<T>::RS;
   constexpr int C = GridCfg<T>::C;
@@ -312,12 +312,20 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
       } else {
         // last Algorithm 2 projection z = P_B(q) with the block's factor,
         // then steps 10-11
-        const double fac = bt.bf.x;
-        const bool inside = bt.bf.y != 0.0;
-        const double mU = mu * bt.U;
-        const double qx = bt.z.x - mU * (bt.z.x - bt.w.x), qy = bt.z.y - mU * (bt.z.y - bt.w.y);
-        const double zx = inside ? qx : double(bt.y.x) + (qx - double(bt.y.x)) * fac;
-        const double zy = inside ? qy : double(bt.y.y) + (qy - double(bt.y.y)) * fac;
+        double zx, zy;
+        if (exact) {
+          // exact prox: (U w + nu y) / (U + nu) with the block's nu, w if nu = 0
+          const double nu = bt.bf.x, inv = 1.0 / (bt.U + nu);
+          zx = nu == 0.0 ? bt.w.x : (bt.U * bt.w.x + nu * double(bt.y.x)) * inv;
+          zy = nu == 0.0 ? bt.w.y : (bt.U * bt.w.y + nu * double(bt.y.y)) * inv;
+        } else {
+          const double fac = bt.bf.x;
+          const bool inside = bt.bf.y != 0.0;
+          const double mU = mu * bt.U;
+          const double qx = bt.z.x - mU * (bt.z.x - bt.w.x), qy = bt.z.y - mU * (bt.z.y - bt.w.y);
+          zx = inside ? qx : double(bt.y.x) + (qx - double(bt.y.x)) * fac;
+          zy = inside ? qy : double(bt.y.y) + (qy - double(bt.y.y)) * fac;
+        }
         znew = make_double2(zx, zy);
         const double vbx = bt.U * (bt.w.x - zx), vby = bt.U * (bt.w.y - zy);
         const float2 vn = make_float2(float(double(bt.v.x) + lambda * (vbx - double(bt.v.x))),
@@ -463,17 +471,17 @@ int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double
 }
 
 template <int T>
-int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, const double* part_in) {
+int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, int exact) {
   if (!dual) {
     hipLaunchKernelGGL((k_grid<T, false>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, vin, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0,
-                       0.0, nullptr);
+                       0.0, nullptr, 0);
   } else {
     hipLaunchKernelGGL((k_grid<T, true>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->wbuf, a->mu,
-                       a->lambda, p->bfac);
+                       a->lambda, p->bfac, exact);
   }
   PPD_HIP(hipGetLastError());
   return PPD_OK;
@@ -502,14 +510,14 @@ int dispatch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, doub
   return timer_end(p, slot);
 }
 
-int dispatch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, const double* part_in) {
+int dispatch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, int exact) {
   int slot;
   PPD_TRY(timer_begin(p, KK_GRID, &slot));
   int st;
   switch (p->T) {
-    case 16: st = launch_grid<16>(p, dual, vin, a, part_in); break;
-    case 32: st = launch_grid<32>(p, dual, vin, a, part_in); break;
-    default: st = launch_grid<64>(p, dual, vin, a, part_in); break;
+    case 16: st = launch_grid<16>(p, dual, vin, a, exact); break;
+    case 32: st = launch_grid<32>(p, dual, vin, a, exact); break;
+    default: st = launch_grid<64>(p, dual, vin, a, exact); break;
   }
   PPD_TRY(st);
   return timer_end(p, slot);
@@ -523,13 +531,18 @@ int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out) {
 }
 
 int grid_plain(ppd_plan* p, const float2* v) {
-  PPD_TRY(dispatch_grid(p, false, v, nullptr, nullptr));
+  PPD_TRY(dispatch_grid(p, false, v, nullptr, 0));
   return fold_grid(p);
 }
 
 int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in) {
   PPD_TRY(block_factors(p, part_in));
-  PPD_TRY(dispatch_grid(p, true, nullptr, &a, part_in));
+  PPD_TRY(dispatch_grid(p, true, nullptr, &a, 0));
+  return fold_grid(p);
+}
+
+int grid_dual_exact(ppd_plan* p, const DualArgs& a) {
+  PPD_TRY(dispatch_grid(p, true, nullptr, &a, 1));
   return fold_grid(p);
 }
 

@@ -177,6 +177,9 @@ int plain_dual(ppd_plan* p, const DualArgs& a);               // per-block unfus
 // Per-block projection factors of P_B from per-segment partials of
 // ||q - y||^2: bfac[j] = (min(1, eps_j / r_j), r_j <= eps_j), r_j the block norm.
 int block_factors(ppd_plan* p, const double* part);
+// n_newton Newton steps of the exact prox per block; nu_j in bfac[j].x.
+int secular_solve(ppd_plan* p, const double2* w, const float2* y, const double* U, int n_newton);
+int grid_dual_exact(ppd_plan* p, const DualArgs& a);   // dual finish with the exact prox + grid
 int permute(ppd_plan* p, int direction, const void* in, void* out, int elem_bytes);
 
 int sara_analysis(ppd_plan* p, const float* x, float* coef, const float* W);

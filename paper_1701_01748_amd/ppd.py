@@ -24,6 +24,7 @@ USER_TO_PLAN, PLAN_TO_USER = 0, 1
 ORDER_PLAN, ORDER_USER = 0, 1
 SARA_ANALYSIS, SARA_SYNTHESIS, SARA_DUAL = 0, 1, 2
 FORM_FUSED, FORM_PLAIN = 0, 1
+PROX_FB, PROX_EXACT = 0, 1
 
 c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -50,7 +51,8 @@ class Params(ctypes.Structure):
     _fields_ = [("tau", c_double), ("eta", c_double), ("zeta", c_double), ("lambda_", c_double),
                 ("alpha", c_double), ("mu", c_double), ("n_itr", c_int32), ("form", c_int32),
                 ("use_graph", c_int32), ("pad_", c_int32), ("y", c_void_p), ("U", c_void_p),
-                ("eps", ctypes.POINTER(c_double)), ("x_true", c_void_p), ("W", c_void_p)]
+                ("eps", ctypes.POINTER(c_double)), ("x_true", c_void_p), ("W", c_void_p),
+                ("prox", c_int32), ("n_newton", c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -75,6 +77,8 @@ _PROTOS = {
     "ppd_reweight": (c_int32, [c_void_p, c_void_p, ctypes.c_float, c_void_p]),
     "ppd_ellipsoid_proj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double),
                                      c_int32, c_double, c_void_p]),
+    "ppd_prox_metric": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_int32,
+                                  c_void_p, c_void_p]),
     "ppd_uniform_weights": (c_int32, [c_void_p, c_void_p]),
     "ppd_op_norm": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_double, ctypes.POINTER(c_double),
                               ctypes.POINTER(c_int32)]),
@@ -321,6 +325,23 @@ def ppd_ellipsoid_proj(plan: Plan, w, y, U, eps, n_itr: int, mu: float, z):
     return z
 
 
+def ppd_prox_metric(plan: Plan, w, y, U, eps, n_newton: int = 12, z=None, nu=None):
+    """Exact prox of eq. elip-proj-1 per block (Newton on the secular equation)."""
+    import torch
+    _need(w, torch.complex128, plan.M, "w")
+    _need(y, torch.complex64, plan.M, "y")
+    _need(U, torch.float64, plan.M, "U")
+    if z is None:
+        z = _alloc((plan.M,), torch.complex128)
+    _need(z, torch.complex128, plan.M, "z")
+    if nu is not None:
+        _need(nu, torch.float64, plan.d, "nu")
+    e, ep = _eps_arg(plan, eps)
+    _check("ppd_prox_metric", lib().ppd_prox_metric(plan.handle, _ptr(w), _ptr(y), _ptr(U), ep, int(n_newton),
+                                                    _ptr(z), _ptr(nu)))
+    return z
+
+
 def ppd_uniform_weights(plan: Plan, U=None):
     import torch
     if U is None:
@@ -366,6 +387,7 @@ class PPDState:
 
 def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49, eta=1.0, zeta=1.0,
                 lam=1.0, alpha=1e-4, mu=1.0, n_itr=1, form=FORM_FUSED, use_graph=False, x_true=None,
+                prox=PROX_FB, n_newton=0,
                 stats: bool = True, W=None):
     """Run n_iter iterations of Algorithm 3; returns a statistics dict (or None)."""
     import torch
@@ -382,7 +404,7 @@ def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49
     e, ep = _eps_arg(plan, eps)
     st = State(_ptr(state.x), _ptr(state.xt), _ptr(state.v), _ptr(state.u), _ptr(state.z), state.iter)
     prm = Params(tau, eta, zeta, lam, alpha, mu, n_itr, form, int(use_graph), 0, _ptr(y), _ptr(U), ep,
-                 _ptr(x_true), _ptr(W))
+                 _ptr(x_true), _ptr(W), int(prox), int(n_newton))
     out = Stats()
     res = (c_double * plan.d)()
     _check("ppd_iterate", lib().ppd_iterate(plan.handle, ctypes.byref(st), ctypes.byref(prm), int(n_iter),

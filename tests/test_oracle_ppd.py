@@ -237,3 +237,34 @@ def test_reweighted_outer_loop_improves_snr():
     h0 = O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, ref, 450, x_true=pb.x_true)
     assert W.shape == (9, 64, 64) and W.max() <= 1.0
     assert hists[-1][-1]["snr"] > h0[-1]["snr"]
+
+
+# ---- exact prox of eq. elip-proj-1 inside Algorithm 3 ----------------------
+
+def test_exact_prox_with_identity_metric_is_pd():
+    """U = I: the exact prox is the Euclidean projection P_B, which Algorithm 2
+    also returns after one step from any start (mu = 1), so the exact-prox
+    iteration reproduces PD."""
+    pb = _weighted_problem(seed=74)
+    n = pb.x_true.shape[0]
+    U1 = np.ones_like(pb.U)
+    a = O.init_state(n, n, pb.y)
+    b = O.init_state(n, n, pb.y)
+    O.iterate(pb.op, pb.y, U1, pb.eps, pb.block_off, O.Params(eta=pb.eta_pd, prox="exact"), a, 8)
+    O.iterate(pb.op, pb.y, U1, pb.eps, pb.block_off, O.Params(eta=pb.eta_pd, n_itr=1), b, 8)
+    assert np.allclose(a.x, b.x, rtol=0, atol=1e-11 * np.abs(b.x).max())
+    assert np.allclose(a.v, b.v, rtol=0, atol=1e-11 * np.abs(b.v).max())
+
+
+def test_exact_prox_is_limit_of_algorithm2():
+    """With many Algorithm 2 steps per iteration the iterates approach the
+    exact-prox iterates (Algorithm 2 converges to prox^U_h)."""
+    pb = _weighted_problem(seed=75)
+    n = pb.x_true.shape[0]
+    a = O.init_state(n, n, pb.y)
+    b = O.init_state(n, n, pb.y)
+    mu = 1.0 / pb.U.max()
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, O.Params(eta=pb.eta, mu=mu, prox="exact"), a, 5)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, O.Params(eta=pb.eta, mu=mu, n_itr=3000), b, 5)
+    assert np.linalg.norm(a.x - b.x) <= 1e-6 * np.linalg.norm(a.x)
+    assert np.linalg.norm(a.z - b.z) <= 1e-6 * np.linalg.norm(a.z)
