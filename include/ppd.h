@@ -209,6 +209,14 @@ typedef struct {
                                       NULL = identity                          */
   int32_t prox;                    /* PPD_PROX_* (0 = Algorithm 2)            */
   int32_t n_newton;                /* Newton steps for PPD_PROX_EXACT (0 -> 12) */
+  const uint8_t* block_active;     /* optional DEVICE [d] active set D of the
+                                      iterations of this call (Algorithm 3
+                                      steps 8, 14-17): block j's v_j and z_j
+                                      are updated only where nonzero; NULL =
+                                      all blocks; fused form only            */
+  const uint8_t* basis_active;     /* optional DEVICE [9] active set P of SARA
+                                      bases (0 = Dirac, p = db-p; steps 18,
+                                      23-26); NULL = all bases               */
 } ppd_params;
 
 typedef struct {

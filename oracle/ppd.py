@@ -65,7 +65,7 @@ class Params:
 
 def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
             x_true: Optional[np.ndarray] = None, W: Optional[np.ndarray] = None,
-            trace: Optional[list] = None):
+            trace: Optional[list] = None, active=None):
     """Run T iterations of Algorithm 3 in place on ``state``.
 
     op: ``oracle.nufft.Nufft``; y, U: (M,) data and preconditioner; eps: (d,)
@@ -75,12 +75,17 @@ def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
     If ``trace`` is a list, each iteration appends what decides its active
     sets -- the clip margins |u + Psi^H x~| - alpha, the arguments of P_C and
     which Algorithm 2 steps project -- i.e. the pieces on which the iteration
-    is smooth."""
+    is smooth.
+    ``active`` (randomised Algorithm 3): None (every block and basis each
+    iteration) or a sequence of T pairs (block_mask (d,), basis_mask (9,)):
+    an inactive block keeps v_j (and its Algorithm 2 iterate), an inactive
+    basis keeps u_i (steps 14-17, 23-26); the random draws are inputs."""
     p = params
     y = np.asarray(y, np.complex128)
     U = np.asarray(U, np.float64)
     hist = []
-    for _ in range(T):
+    for t in range(T):
+        bmask, pmask = (None, None) if active is None else active[t]
         a = op.fft_grid(state.xt)                          # step 4: a = F Z x tilde
         Ga = op.degrid(a)                                  # Theta_j G_j M_j a, all j
         v_new = state.v.copy()
@@ -90,6 +95,9 @@ def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
         for j in range(len(block_off) - 1):                # steps 9-13, all blocks
             s = slice(int(block_off[j]), int(block_off[j + 1]))
             res.append(np.linalg.norm(Ga[s] - y[s]))
+            if bmask is not None and not bmask[j]:         # steps 14-17: v_j, z_j kept
+                sets_proj.append(())
+                continue
             w = state.v[s] / U[s] + Ga[s]
             if p.prox == "exact":                          # eq. elip-proj-1 solved exactly
                 z = prox.prox_metric_exact(w, y[s], eps[j], U[s])
@@ -113,6 +121,9 @@ def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
             coef = W * coef
         ubar = prox.clip_dual(state.u + coef, p.alpha)     # step 19
         u_new = state.u + p.lam * (ubar - state.u)         # step 20
+        if pmask is not None:                              # steps 23-26: u_i kept
+            keep = ~np.asarray(pmask, dtype=bool)
+            u_new[keep] = state.u[keep]
         ut = sara.synthesis(u_new if W is None else W * u_new, p.levels)  # step 21, summed
         arg = state.x - p.tau * (p.eta * op.ifft_grid_real(vt) + p.zeta * ut)
         xbar = prox.proj_C(arg)                            # step 28

@@ -29,7 +29,8 @@ constexpr int ALG2_WAVES = 4;
 __global__ __launch_bounds__(64 * ALG2_WAVES) void k_alg2(
     int mode, const Item* __restrict__ items, int n_items, const Seg* __restrict__ segs,
     const double2* __restrict__ w, const float2* __restrict__ y, const double* __restrict__ U,
-    double2* __restrict__ z, double mu, const double2* __restrict__ bfac, double* __restrict__ part_out) {
+    double2* __restrict__ z, double mu, const double2* __restrict__ bfac, const uint8_t* __restrict__ active,
+    double* __restrict__ part_out) {
   constexpr int NW = ALG2_WAVES;
   __shared__ ItemTab tab;
   __shared__ double s_q[NW][MAX_ITEM_SEGS];
@@ -56,7 +57,8 @@ __global__ __launch_bounds__(64 * ALG2_WAVES) void k_alg2(
       double2 ze = z[pi];
       const double mU = mu * U[pi];
       const float2 ye = y[pi];
-      if (mode != 0) {
+      // randomised updates (Algorithm 3 steps 14-17): an inactive block keeps z
+      if (mode != 0 && (!active || active[tab.block[sg]])) {
         const double2 bf = bfac[tab.block[sg]];
         const double qx = ze.x - mU * (ze.x - we.x), qy = ze.y - mU * (ze.y - we.y);
         ze.x = bf.y != 0.0 ? qx : double(ye.x) + (qx - double(ye.x)) * bf.x;
@@ -385,12 +387,12 @@ int grid_blocks(int64_t n) { return int(std::min<int64_t>((n + PL_THREADS - 1) /
 }  // namespace
 
 int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* y, const double* U, double2* z,
-                double mu, const double* part_in, double* part_out) {
+                double mu, const double* part_in, double* part_out, const uint8_t* active) {
   if (mode != 0) PPD_TRY(block_factors(p, part_in));
   int slot;
   PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
   hipLaunchKernelGGL(k_alg2, dim3(p->n_launch), dim3(64 * ALG2_WAVES), 0, p->stream, mode, p->items, p->n_items,
-                     p->segs, w, y, U, z, mu, p->bfac, part_out);
+                     p->segs, w, y, U, z, mu, p->bfac, active, part_out);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }
@@ -464,12 +466,12 @@ extern "C" int ppd_ellipsoid_proj(ppd_plan* p, const double* w, const float* y, 
   double2* z2 = reinterpret_cast<double2*>(zbar);
   double* pa = p->part;
   double* pb = p->part + p->n_segs;
-  PPD_TRY(alg2_launch(p, 0, w2, y2, U, z2, mu, nullptr, pa));
+  PPD_TRY(alg2_launch(p, 0, w2, y2, U, z2, mu, nullptr, pa, nullptr));
   for (int s = 1; s < n_itr; ++s) {
-    PPD_TRY(alg2_launch(p, 1, w2, y2, U, z2, mu, pa, pb));
+    PPD_TRY(alg2_launch(p, 1, w2, y2, U, z2, mu, pa, pb, nullptr));
     std::swap(pa, pb);
   }
-  return alg2_launch(p, 2, w2, y2, U, z2, mu, pa, nullptr);
+  return alg2_launch(p, 2, w2, y2, U, z2, mu, pa, nullptr, nullptr);
 }
 
 extern "C" int ppd_prox_metric(ppd_plan* p, const double* w, const float* y, const double* U, const double* eps,

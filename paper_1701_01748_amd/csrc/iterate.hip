@@ -11,7 +11,7 @@ namespace ppd {
 
 int primal_partial_count(ppd_plan* p);
 int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* y, const double* U, double2* z,
-                double mu, const double* part_in, double* part_out);
+                double mu, const double* part_in, double* part_out, const uint8_t* active);
 
 namespace {
 
@@ -121,6 +121,7 @@ struct IterCtx {
   float alpha, lambda;
   int form;
   int prox, n_newton;
+  const uint8_t* basis_active;
 };
 
 // Runs the plan's launches on another stream for the lifetime of the object.
@@ -142,7 +143,7 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
   PPD_HIP(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
   {
     OnStream on(p, p->aux);
-    PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda, c.W));   // steps 19-20
+    PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda, c.W, c.basis_active));   // steps 19-20
     PPD_TRY(sara_synthesis(p, c.u, p->ut, c.W));              // step 21, summed over i
     PPD_HIP(hipEventRecord(p->ev_join, p->aux));
   }
@@ -156,7 +157,7 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
     double* pb = p->part + p->n_segs;
     PPD_TRY(degrid_dual(p, c.dual, pa));                    // step 10 argument, first Alg. 2 step
     for (int s = 1; s < c.dual.n_itr; ++s) {
-      PPD_TRY(alg2_launch(p, 1, p->wbuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb));
+      PPD_TRY(alg2_launch(p, 1, p->wbuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb, c.dual.active));
       std::swap(pa, pb);
     }
     PPD_TRY(grid_dual(p, c.dual, pa));                      // steps 10-12
@@ -172,9 +173,10 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
 
 std::string graph_key(const IterCtx& c) {
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d %d %d",
+  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d %d %d",
                 (void*)c.dual.y, (void*)c.dual.U, (void*)c.dual.v, (void*)c.dual.z, (void*)c.primal.x,
-                (void*)c.primal.xt, (void*)c.primal.x_true, (void*)c.u, (void*)c.primal.ut, (void*)c.W, c.dual.mu,
+                (void*)c.primal.xt, (void*)c.primal.x_true, (void*)c.u, (void*)c.primal.ut, (void*)c.W,
+                (const void*)c.dual.active, (const void*)c.basis_active, c.dual.mu,
                 c.dual.lambda, c.primal.tau, c.primal.eta, c.primal.zeta, double(c.alpha),
                 double(c.lambda), c.dual.n_itr, c.form, c.prox, c.n_newton);
   return std::string(buf);
@@ -210,6 +212,8 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   if (prm->prox == PPD_PROX_EXACT && prm->form != PPD_FORM_FUSED)
     return fail(PPD_EUNSUPPORTED, "ppd_iterate: the exact prox is implemented in the fused form only");
   if (prm->n_newton < 0 || prm->n_newton > 64) return fail(PPD_EINVAL, "ppd_iterate: n_newton must be in [0, 64]");
+  if (prm->block_active && prm->form != PPD_FORM_FUSED)
+    return fail(PPD_EUNSUPPORTED, "ppd_iterate: randomised block updates are implemented in the fused form only");
   const double vals[6] = {prm->tau, prm->eta, prm->zeta, prm->lambda, prm->alpha, prm->mu};
   for (double v : vals)
     if (!std::isfinite(v)) return fail(PPD_EINVAL, "ppd_iterate: non-finite parameter");
@@ -243,6 +247,8 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   c.lambda = float(prm->lambda);
   c.form = prm->form;
   c.prox = prm->prox;
+  c.dual.active = prm->block_active;
+  c.basis_active = prm->basis_active;
   c.n_newton = prm->n_newton == 0 ? 12 : prm->n_newton;
 
   if (n_iter > 0) {

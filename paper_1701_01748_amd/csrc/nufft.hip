@@ -228,7 +228,7 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
     const float2* __restrict__ vin, const float2* __restrict__ y, const double* __restrict__ U,
     float2* __restrict__ v, double2* __restrict__ z, const double2* __restrict__ w, double mu,
-    double lambda, const double2* __restrict__ bfac, int exact) {
+    double lambda, const double2* __restrict__ bfac, int exact, const uint8_t* __restrict__ active) {
   constexpr int R = GridCfg<T>::R;
   constexpr int RS = GridCfg<T>::RS;
   constexpr int C = GridCfg<T>::C;
@@ -264,6 +264,7 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     double2 w, z, bf;
     double U;
     int pi;
+    bool act;
   };
   const int nseg = it.seg1 - it.seg0;
   const int total = tab.pre[nseg];
@@ -286,6 +287,7 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
         b.y = y[pi];
         b.v = v[pi];
         b.bf = bfac[tab.block[sg]];
+        b.act = !active || active[tab.block[sg]];
       }
     }
   };
@@ -309,6 +311,9 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
       float2 val;
       if (!DUAL) {
         val = bt.vin;
+      } else if (!bt.act) {
+        // randomised updates (steps 14-17): an inactive block keeps v and z
+        val = bt.v;
       } else {
         // last Algorithm 2 projection z = P_B(q) with the block's factor,
         // then steps 10-11
@@ -376,7 +381,7 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
       }
     }
     __builtin_amdgcn_wave_barrier();
-    if (DUAL && lane < nb) {
+    if (DUAL && lane < nb && bt.act) {
       z[bt.pi] = znew;
       v[bt.pi] = vnew;
     }
@@ -476,12 +481,12 @@ int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, in
     hipLaunchKernelGGL((k_grid<T, false>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, vin, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0,
-                       0.0, nullptr, 0);
+                       0.0, nullptr, 0, nullptr);
   } else {
     hipLaunchKernelGGL((k_grid<T, true>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->wbuf, a->mu,
-                       a->lambda, p->bfac, exact);
+                       a->lambda, p->bfac, exact, a->active);
   }
   PPD_HIP(hipGetLastError());
   return PPD_OK;

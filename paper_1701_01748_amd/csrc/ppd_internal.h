@@ -168,6 +168,7 @@ struct DualArgs {
   const float2* y; const double* U; float2* v; double2* z;
   double mu, lambda;
   int n_itr;
+  const uint8_t* active;   // DEVICE [d] block mask of this iteration, NULL = all
 };
 int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out);   // grid_f -> wbuf
 int grid_plain(ppd_plan* p, const float2* v);                 // v -> grid_a (accumulate)
@@ -183,7 +184,8 @@ int grid_dual_exact(ppd_plan* p, const DualArgs& a);   // dual finish with the e
 int permute(ppd_plan* p, int direction, const void* in, void* out, int elem_bytes);
 
 int sara_analysis(ppd_plan* p, const float* x, float* coef, const float* W);
-int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda, const float* W);
+int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda, const float* W,
+              const uint8_t* active = nullptr);   // active: DEVICE [9] basis mask, NULL = all
 int sara_synthesis(ppd_plan* p, const float* u, float* out, const float* W);
 
 int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq);

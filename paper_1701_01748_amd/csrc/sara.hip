@@ -139,13 +139,14 @@ __device__ void dwt_tile(const float* __restrict__ src, int sstride, float scale
 static_assert(AT * AT <= 256, "an analysis tile must fit one output per thread of 256");
 
 // Level l of the 8 wavelet bases (blockIdx.z = basis - 1); at level 1 the
-// Dirac basis is blockIdx.z = 8.  Level 1 reads the image scaled by 1/3,
+// Dirac basis is blockIdx.z = 8.  `active` (dual mode, may be NULL) masks
+// the bases updated this iteration.  Level 1 reads the image scaled by 1/3,
 // deeper levels the low-pass band of the previous level.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float* __restrict__ tmp,
                                              float* __restrict__ out, const float* __restrict__ filt,
                                              const float* __restrict__ W, SaraGeom g, int l, float alpha,
-                                             float lambda) {
+                                             float lambda, const uint8_t* __restrict__ active) {
   __shared__ float s_in[SIN * SIN];
   __shared__ float s_lo[AT * SIN];
   __shared__ float s_hi[AT * SIN];
@@ -155,6 +156,9 @@ __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float*
   const int k0y = blockIdx.y * toy, k0x = blockIdx.x * tox;
   const int q = blockIdx.z + 1;   // 1..8 wavelets, 9 = Dirac (level 1 only)
   const float third = 1.0f / 3.0f;
+  // randomised updates (Algorithm 3 steps 23-26): an inactive basis keeps
+  // its u_i (basis index 0 is the Dirac basis)
+  if (active && !active[q == 9 ? 0 : q]) return;
   if (q == 9) {
     // Dirac basis: coefficient x / 3 at every pixel of this tile's footprint
     // (at most 4 pixels per thread; all loads issued first)
@@ -495,7 +499,7 @@ SaraGeom geom(const ppd_plan* p) {
 }
 
 int analysis_launch(ppd_plan* p, const float* x, float* out, const float* W, bool dual, float alpha,
-                    float lambda) {
+                    float lambda, const uint8_t* active) {
   const SaraGeom g = geom(p);
   for (int l = 1; l <= g.L; ++l) {
     const int oh = (g.ny >> l), ow = (g.nx >> l);
@@ -505,10 +509,10 @@ int analysis_launch(ppd_plan* p, const float* x, float* out, const float* W, boo
     PPD_TRY(timer_begin(p, KK_DWT, &slot));
     if (dual)
       hipLaunchKernelGGL(k_dwt<A_DUAL>, grid, dim3(256), 0, p->stream, x, p->sara_ll, out, p->filt, W, g, l,
-                         alpha, lambda);
+                         alpha, lambda, active);
     else
       hipLaunchKernelGGL(k_dwt<A_PLAIN>, grid, dim3(256), 0, p->stream, x, p->sara_ll, out, p->filt, W, g, l,
-                         alpha, lambda);
+                         alpha, lambda, nullptr);
     PPD_HIP(hipGetLastError());
     PPD_TRY(timer_end(p, slot));
   }
@@ -518,11 +522,12 @@ int analysis_launch(ppd_plan* p, const float* x, float* out, const float* W, boo
 }  // namespace
 
 int sara_analysis(ppd_plan* p, const float* x, float* coef, const float* W) {
-  return analysis_launch(p, x, coef, W, false, 0.f, 0.f);
+  return analysis_launch(p, x, coef, W, false, 0.f, 0.f, nullptr);
 }
 
-int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda, const float* W) {
-  return analysis_launch(p, x, u, W, true, alpha, lambda);
+int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda, const float* W,
+              const uint8_t* active) {
+  return analysis_launch(p, x, u, W, true, alpha, lambda, active);
 }
 
 int sara_synthesis(ppd_plan* p, const float* u, float* out, const float* W) {

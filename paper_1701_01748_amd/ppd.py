@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
                 ("alpha", c_double), ("mu", c_double), ("n_itr", c_int32), ("form", c_int32),
                 ("use_graph", c_int32), ("pad_", c_int32), ("y", c_void_p), ("U", c_void_p),
                 ("eps", ctypes.POINTER(c_double)), ("x_true", c_void_p), ("W", c_void_p),
-                ("prox", c_int32), ("n_newton", c_int32)]
+                ("prox", c_int32), ("n_newton", c_int32), ("block_active", c_void_p),
+                ("basis_active", c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -387,7 +388,7 @@ class PPDState:
 
 def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49, eta=1.0, zeta=1.0,
                 lam=1.0, alpha=1e-4, mu=1.0, n_itr=1, form=FORM_FUSED, use_graph=False, x_true=None,
-                prox=PROX_FB, n_newton=0,
+                prox=PROX_FB, n_newton=0, block_active=None, basis_active=None,
                 stats: bool = True, W=None):
     """Run n_iter iterations of Algorithm 3; returns a statistics dict (or None)."""
     import torch
@@ -401,10 +402,14 @@ def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49
         _need(x_true, torch.float32, plan.N, "x_true")
     if W is not None:
         _need(W, torch.float32, 9 * plan.N, "W")
+    if block_active is not None:
+        _need(block_active, torch.uint8, plan.d, "block_active")
+    if basis_active is not None:
+        _need(basis_active, torch.uint8, 9, "basis_active")
     e, ep = _eps_arg(plan, eps)
     st = State(_ptr(state.x), _ptr(state.xt), _ptr(state.v), _ptr(state.u), _ptr(state.z), state.iter)
     prm = Params(tau, eta, zeta, lam, alpha, mu, n_itr, form, int(use_graph), 0, _ptr(y), _ptr(U), ep,
-                 _ptr(x_true), _ptr(W), int(prox), int(n_newton))
+                 _ptr(x_true), _ptr(W), int(prox), int(n_newton), _ptr(block_active), _ptr(basis_active))
     out = Stats()
     res = (c_double * plan.d)()
     _check("ppd_iterate", lib().ppd_iterate(plan.handle, ctypes.byref(st), ctypes.byref(prm), int(n_iter),
@@ -414,6 +419,30 @@ def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49
         return None
     return {"iter": int(out.iter), "rel_change": out.rel_change, "x_norm": out.x_norm,
             "snr_db": out.snr_db, "residual_max": out.residual_max, "residual": np.array(res[:])}
+
+
+def randomised_ppd(plan: Plan, state: PPDState, y, U, eps, block_masks, basis_masks, **kw):
+    """Algorithm 3 with random active sets: iteration t updates the blocks
+    with block_masks[t] != 0 and the bases with basis_masks[t] != 0 (HOST
+    uint8 arrays T x d and T x 9).  The masks go to two device buffers that
+    every call reads, so a captured graph replays with the current draw.
+    Returns the statistics of the last iteration."""
+    import torch
+    bm = np.ascontiguousarray(block_masks, dtype=np.uint8)
+    pm = np.ascontiguousarray(basis_masks, dtype=np.uint8)
+    if bm.ndim != 2 or bm.shape[1] != plan.d or pm.shape != (bm.shape[0], 9):
+        raise ValueError("block_masks must be T x d and basis_masks T x 9")
+    dev_b = torch.empty(plan.d, dtype=torch.uint8, device="cuda")
+    dev_p = torch.empty(9, dtype=torch.uint8, device="cuda")
+    stats = kw.pop("stats", True)
+    out = None
+    for t in range(bm.shape[0]):
+        dev_b.copy_(torch.from_numpy(bm[t]), non_blocking=False)
+        dev_p.copy_(torch.from_numpy(pm[t]), non_blocking=False)
+        last = t == bm.shape[0] - 1
+        out = ppd_iterate(plan, state, y, U, eps, 1, block_active=dev_b, basis_active=dev_p,
+                          stats=stats and last, **kw)
+    return out
 
 
 def reweighted_ppd(plan: Plan, state: PPDState, y, U, eps, n_reweights: int, iters_per_solve: int,

@@ -69,6 +69,16 @@ WORKLOADS = {
     "multichan512": Workload("multichan512", n=512, M=1_000_000, d=8, coverage="radial",
                              isnr_db=30.0, seed_idx=4, n_chan=8,
                              rmax=math.pi / 1.1, block_lo=60_000, block_hi=250_000),
+    # 256^2, 65536 points drawn from a generalised Gaussian of shape beta in u
+    # and v (Sec. 5.2: beta = 2, 0.5, 0.25; input SNR 30 and 50 dB), 4 blocks.
+    "ggd256_b2": Workload("ggd256_b2", n=256, M=65536, d=4, coverage="ggd", isnr_db=30.0,
+                          seed_idx=6, block_lo=8000, block_hi=30000, ggd_beta=2.0, iters=300),
+    "ggd256_b05": Workload("ggd256_b05", n=256, M=65536, d=4, coverage="ggd", isnr_db=30.0,
+                           seed_idx=7, block_lo=8000, block_hi=30000, ggd_beta=0.5, iters=300),
+    "ggd256_b025": Workload("ggd256_b025", n=256, M=65536, d=4, coverage="ggd", isnr_db=30.0,
+                            seed_idx=8, block_lo=8000, block_hi=30000, ggd_beta=0.25, iters=300),
+    "ggd256_b025_50db": Workload("ggd256_b025_50db", n=256, M=65536, d=4, coverage="ggd", isnr_db=50.0,
+                                 seed_idx=8, block_lo=8000, block_hi=30000, ggd_beta=0.25, iters=300),
     # 2048^2, 20M points, 64 uneven blocks, 1e3:1 density contrast.
     "ppd2048": Workload("ppd2048", n=2048, M=20_000_000, d=64, coverage="radial",
                         isnr_db=30.0, seed_idx=5,
@@ -158,6 +168,16 @@ def coverage_ggd(M: int, seed: int, beta: float, scale: float = 0.3 * math.pi):
             vals = np.concatenate([vals, x[np.abs(x) < PI_F32_BELOW]])
         out.append(vals[:M])
     return _to_f32_coverage(out[0], out[1])
+
+
+def active_sets(T: int, d: int, p_block: float, p_basis: float, seed: int, n_bases: int = 9):
+    """Random active sets of a randomised run (Sec. 4: independent, identically
+    distributed draws with nonzero probability): T x d block masks and
+    T x n_bases basis masks, Bernoulli(p_block) and Bernoulli(p_basis), uint8."""
+    rng = np.random.default_rng(seed)
+    blocks = (rng.uniform(size=(T, d)) < p_block).astype(np.uint8)
+    bases = (rng.uniform(size=(T, n_bases)) < p_basis).astype(np.uint8)
+    return blocks, bases
 
 
 def noise_unit(M: int, seed: int) -> np.ndarray:

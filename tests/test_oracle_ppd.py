@@ -268,3 +268,57 @@ def test_exact_prox_is_limit_of_algorithm2():
     O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, O.Params(eta=pb.eta, mu=mu, n_itr=3000), b, 5)
     assert np.linalg.norm(a.x - b.x) <= 1e-6 * np.linalg.norm(a.x)
     assert np.linalg.norm(a.z - b.z) <= 1e-6 * np.linalg.norm(a.z)
+
+
+# ---- randomised active sets (Algorithm 3 steps 8, 14-17, 23-26) -----------
+
+def test_all_active_masks_equal_full_iteration():
+    pb = _weighted_problem(seed=76)
+    n, d = pb.x_true.shape[0], len(pb.eps)
+    T = 5
+    a = O.init_state(n, n, pb.y)
+    b = O.init_state(n, n, pb.y)
+    masks = [(np.ones(d, np.uint8), np.ones(9, np.uint8))] * T
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, O.Params(eta=pb.eta), a, T, active=masks)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, O.Params(eta=pb.eta), b, T)
+    for k in ("x", "xt", "v", "u", "z"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
+
+
+def test_never_active_basis_equals_zero_weight():
+    """A basis that is never active keeps u_i = 0, which is what a zero
+    re-weight W_i does through the clip and the synthesis."""
+    pb = _weighted_problem(seed=77)
+    n, d = pb.x_true.shape[0], len(pb.eps)
+    T = 6
+    pm = np.ones(9, np.uint8)
+    pm[4] = 0
+    a = O.init_state(n, n, pb.y)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, O.Params(eta=pb.eta), a, T,
+              active=[(np.ones(d, np.uint8), pm)] * T)
+    W = np.ones((9, n, n))
+    W[4] = 0.0
+    b = O.init_state(n, n, pb.y)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, O.Params(eta=pb.eta), b, T, W=W)
+    assert np.array_equal(a.x, b.x)
+    assert np.abs(a.u[4]).max() == 0.0
+
+
+def test_never_active_block_equals_dropping_its_data():
+    """A data block that is never active keeps v_j = 0: the run equals the
+    one on the problem without that block's visibilities."""
+    from oracle import nufft as onf
+    pb = _weighted_problem(seed=78)
+    n = pb.x_true.shape[0]
+    off = pb.block_off
+    T = 6
+    a = O.init_state(n, n, pb.y)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, off, O.Params(eta=pb.eta), a, T,
+              active=[(np.array([1, 0], np.uint8), np.ones(9, np.uint8))] * T)
+    keep = slice(int(off[0]), int(off[1]))
+    _, wu, wv, _ = synth.small_case(32, 1500, seed=78, d=2)     # the coverage of _weighted_problem
+    op0 = onf.Nufft(wu[keep], wv[keep], n, n)
+    b = O.init_state(n, n, pb.y[keep])
+    O.iterate(op0, pb.y[keep], pb.U[keep], pb.eps[:1], off[:2], O.Params(eta=pb.eta), b, T)
+    assert np.allclose(a.x, b.x, rtol=0, atol=1e-12 * np.abs(b.x).max())
+    assert np.abs(a.v[int(off[1]):]).max() == 0.0
