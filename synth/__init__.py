@@ -153,18 +153,22 @@ def coverage_tracks(M: int, seed: int, n_tracks: int = 36, jitter: float = 0.002
     return _to_f32_coverage(np.concatenate(us), np.concatenate(vs))
 
 
-def coverage_ggd(M: int, seed: int, beta: float, scale: float = 0.3 * math.pi):
+def coverage_ggd(M: int, seed: int, beta: float, std: float = math.pi / 3):
     """Zero-mean generalised Gaussian in u and v independently, shape beta
-    (beta = 2 Gaussian; smaller beta = heavier centre and tails).  Samples
-    outside [-pi, pi) are redrawn."""
+    (beta = 2 Gaussian; smaller beta = sharper centre and heavier tails),
+    scale set so that the standard deviation is `std` for every beta:
+    x = s * alpha * g^(1/beta), g ~ Gamma(1/beta), s = +-1, alpha =
+    std * sqrt(Gamma(1/beta) / Gamma(3/beta)).  Samples outside [-pi, pi)
+    are redrawn."""
     rng = np.random.default_rng(seed)
+    alpha = std * math.exp(0.5 * (math.lgamma(1.0 / beta) - math.lgamma(3.0 / beta)))
     out = []
     for _ in range(2):
         vals = np.empty(0)
         while vals.size < M:
             g = rng.gamma(1.0 / beta, 1.0, size=2 * M)
             sgn = np.where(rng.uniform(size=2 * M) < 0.5, -1.0, 1.0)
-            x = sgn * scale * g ** (1.0 / beta)
+            x = sgn * alpha * g ** (1.0 / beta)
             vals = np.concatenate([vals, x[np.abs(x) < PI_F32_BELOW]])
         out.append(vals[:M])
     return _to_f32_coverage(out[0], out[1])
