@@ -256,6 +256,32 @@ def make_inputs(w: Workload) -> Inputs:
     return Inputs(w, x, wu, wv, off, nz, ps)
 
 
+def crop_inputs(big: Inputs, n_crop: int, keep: int, seed: int) -> Inputs:
+    """A smaller problem at the same visibilities-per-grid-cell density as a
+    large workload: the central n_crop x n_crop part of its sky and a random
+    1/keep subset of its points (frequencies in radians per pixel, so the
+    same values index the smaller grid at the same relative place), with the
+    block structure kept (each block subsampled alike) and fresh unit noise."""
+    w = big.workload
+    n = w.n
+    r0 = (n - n_crop) // 2
+    x = big.x_true[r0:r0 + n_crop, r0:r0 + n_crop].copy()
+    rng = np.random.default_rng(seed)
+    wu, wv, off = big.wu[0], big.wv[0], big.block_off
+    idx, new_off = [], [0]
+    for j in range(off.size - 1):
+        pick = np.sort(rng.choice(np.arange(off[j], off[j + 1]), size=(off[j + 1] - off[j]) // keep,
+                                  replace=False))
+        idx.append(pick)
+        new_off.append(new_off[-1] + pick.size)
+    idx = np.concatenate(idx)
+    M = idx.size
+    cw = dataclasses.replace(w, name=f"{w.name}_crop{n_crop}", n=n_crop, M=M)
+    nz = noise_unit(M, seed=seed + 1)[None, :]
+    ps = np.random.default_rng(seed + 2).standard_normal((n_crop, n_crop))
+    return Inputs(cw, x, wu[idx][None, :], wv[idx][None, :], np.asarray(new_off, dtype=np.int64), nz, ps)
+
+
 def small_case(n: int, M: int, seed: int, nx: Optional[int] = None, d: int = 1,
                coverage: str = "radial"):
     """Tiny random problem for unit tests: (x, wu, wv, block_off)."""
