@@ -69,10 +69,10 @@ def measured_traffic(kind: str, workload: str, tile: int, chunk: int):
 
 def algorithmic_bytes(kind: str, M: int, N: int, K: int, ny: int, Kx: int) -> float:
     """Bytes each kernel kind must move per launch (fused PPD iteration)."""
-    if kind == "degrid":      # omega 8, v 8, U 8, z 16, y 8 in; w 16 out; grid read once
-        return 64.0 * M + 8.0 * K
-    if kind == "grid":        # omega 8, w 16, z 16, U 8, y 8, v 8 in; z 16, v 8 out; grid written once
-        return 88.0 * M + 8.0 * K
+    if kind == "degrid":      # omega 8, v 8, U 8, z 16, y 8 in; Theta G a 8 out; grid read once
+        return 56.0 * M + 8.0 * K
+    if kind == "grid":        # omega 8, Theta G a 8, z 16, U 8, y 8, v 8 in; z 16, v 8 out; grid written once
+        return 80.0 * M + 8.0 * K
     if kind == "fft_rows_fwd":
         return 4.0 * N + 8.0 * ny * Kx
     if kind in ("fft_cols_fwd", "fft_cols_inv"):

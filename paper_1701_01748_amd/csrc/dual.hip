@@ -28,7 +28,8 @@ __device__ inline double block_sum(double v, double* red) {
 constexpr int ALG2_WAVES = 4;
 __global__ __launch_bounds__(64 * ALG2_WAVES) void k_alg2(
     int mode, const Item* __restrict__ items, int n_items, const Seg* __restrict__ segs,
-    const double2* __restrict__ w, const float2* __restrict__ y, const double* __restrict__ U,
+    const double2* __restrict__ w, const float2* __restrict__ v, const float2* __restrict__ ga,
+    const float2* __restrict__ y, const double* __restrict__ U,
     double2* __restrict__ z, double mu, const double2* __restrict__ bfac, const uint8_t* __restrict__ active,
     double* __restrict__ part_out) {
   constexpr int NW = ALG2_WAVES;
@@ -53,9 +54,10 @@ __global__ __launch_bounds__(64 * ALG2_WAVES) void k_alg2(
     double qn = 0.0;
     if (act) {
       const int pi = tab.start[sg] + (li - tab.pre[sg]);
-      const double2 we = w[pi];
+      const double Ue = U[pi];
+      const double2 we = w ? w[pi] : dual_arg(v[pi], Ue, ga[pi]);
       double2 ze = z[pi];
-      const double mU = mu * U[pi];
+      const double mU = mu * Ue;
       const float2 ye = y[pi];
       // randomised updates (Algorithm 3 steps 14-17): an inactive block keeps z
       if (mode != 0 && (!active || active[tab.block[sg]])) {
@@ -135,8 +137,9 @@ __global__ __launch_bounds__(256) void k_block_factors(const double* __restrict_
 constexpr int SEC_WAVES = 4;
 __global__ __launch_bounds__(64 * SEC_WAVES) void k_sec_partials(
     const Item* __restrict__ items, int n_items, const Seg* __restrict__ segs, const double2* __restrict__ w,
-    const float2* __restrict__ y, const double* __restrict__ U, const double2* __restrict__ bfac, int first,
-    double* __restrict__ p2, double* __restrict__ p3) {
+    const float2* __restrict__ v, const float2* __restrict__ ga, const float2* __restrict__ y,
+    const double* __restrict__ U, const double2* __restrict__ bfac, int first, double* __restrict__ p2,
+    double* __restrict__ p3) {
   constexpr int NW = SEC_WAVES;
   __shared__ ItemTab tab;
   __shared__ double s2[NW][MAX_ITEM_SEGS], s3[NW][MAX_ITEM_SEGS];
@@ -162,9 +165,9 @@ __global__ __launch_bounds__(64 * SEC_WAVES) void k_sec_partials(
     double t2 = 0.0, t3 = 0.0;
     if (act) {
       const int pi = tab.start[sg] + (li - tab.pre[sg]);
-      const double2 we = w[pi];
-      const float2 ye = y[pi];
       const double Ue = U[pi];
+      const double2 we = w ? w[pi] : dual_arg(v[pi], Ue, ga[pi]);
+      const float2 ye = y[pi];
       const double nu = first ? 0.0 : bfac[tab.block[sg]].x;
       const double dx = we.x - double(ye.x), dy = we.y - double(ye.y);
       const double a2 = Ue * Ue * (dx * dx + dy * dy);
@@ -386,25 +389,27 @@ int grid_blocks(int64_t n) { return int(std::min<int64_t>((n + PL_THREADS - 1) /
 
 }  // namespace
 
-int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* y, const double* U, double2* z,
-                double mu, const double* part_in, double* part_out, const uint8_t* active) {
+int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* v, const float2* ga, const float2* y,
+                const double* U, double2* z, double mu, const double* part_in, double* part_out,
+                const uint8_t* active) {
   if (mode != 0) PPD_TRY(block_factors(p, part_in));
   int slot;
   PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
   hipLaunchKernelGGL(k_alg2, dim3(p->n_launch), dim3(64 * ALG2_WAVES), 0, p->stream, mode, p->items, p->n_items,
-                     p->segs, w, y, U, z, mu, p->bfac, active, part_out);
+                     p->segs, w, v, ga, y, U, z, mu, p->bfac, active, part_out);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }
 
-int secular_solve(ppd_plan* p, const double2* w, const float2* y, const double* U, int n_newton) {
+int secular_solve(ppd_plan* p, const double2* w, const float2* v, const float2* ga, const float2* y,
+                  const double* U, int n_newton) {
   double* p2 = p->part;
   double* p3 = p->part + p->n_segs;
   for (int s = 0; s < n_newton; ++s) {
     int slot;
     PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
     hipLaunchKernelGGL(k_sec_partials, dim3(p->n_launch), dim3(64 * SEC_WAVES), 0, p->stream, p->items,
-                       p->n_items, p->segs, w, y, U, p->bfac, int(s == 0), p2, p3);
+                       p->n_items, p->segs, w, v, ga, y, U, p->bfac, int(s == 0), p2, p3);
     PPD_HIP(hipGetLastError());
     PPD_TRY(timer_end(p, slot));
     PPD_TRY(timer_begin(p, KK_MISC, &slot));
@@ -466,12 +471,12 @@ extern "C" int ppd_ellipsoid_proj(ppd_plan* p, const double* w, const float* y, 
   double2* z2 = reinterpret_cast<double2*>(zbar);
   double* pa = p->part;
   double* pb = p->part + p->n_segs;
-  PPD_TRY(alg2_launch(p, 0, w2, y2, U, z2, mu, nullptr, pa, nullptr));
+  PPD_TRY(alg2_launch(p, 0, w2, nullptr, nullptr, y2, U, z2, mu, nullptr, pa, nullptr));
   for (int s = 1; s < n_itr; ++s) {
-    PPD_TRY(alg2_launch(p, 1, w2, y2, U, z2, mu, pa, pb, nullptr));
+    PPD_TRY(alg2_launch(p, 1, w2, nullptr, nullptr, y2, U, z2, mu, pa, pb, nullptr));
     std::swap(pa, pb);
   }
-  return alg2_launch(p, 2, w2, y2, U, z2, mu, pa, nullptr, nullptr);
+  return alg2_launch(p, 2, w2, nullptr, nullptr, y2, U, z2, mu, pa, nullptr, nullptr);
 }
 
 extern "C" int ppd_prox_metric(ppd_plan* p, const double* w, const float* y, const double* U, const double* eps,
@@ -481,7 +486,7 @@ extern "C" int ppd_prox_metric(ppd_plan* p, const double* w, const float* y, con
   PPD_TRY(upload_eps(p, eps));
   const double2* w2 = reinterpret_cast<const double2*>(w);
   const float2* y2 = reinterpret_cast<const float2*>(y);
-  PPD_TRY(secular_solve(p, w2, y2, U, n_newton));
+  PPD_TRY(secular_solve(p, w2, nullptr, nullptr, y2, U, n_newton));
   int slot;
   PPD_TRY(timer_begin(p, KK_MISC, &slot));
   hipLaunchKernelGGL(k_prox_apply, dim3(int(std::min<int64_t>((p->M + 255) / 256, 4096))), dim3(256), 0, p->stream,

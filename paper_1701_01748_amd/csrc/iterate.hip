@@ -10,8 +10,9 @@
 namespace ppd {
 
 int primal_partial_count(ppd_plan* p);
-int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* y, const double* U, double2* z,
-                double mu, const double* part_in, double* part_out, const uint8_t* active);
+int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* v, const float2* ga, const float2* y,
+                const double* U, double2* z, double mu, const double* part_in, double* part_out,
+                const uint8_t* active);
 
 namespace {
 
@@ -150,14 +151,15 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
   PPD_TRY(fft_forward(p, xt));                              // step 4: a = F Z x~
   if (c.form == PPD_FORM_FUSED && c.prox == PPD_PROX_EXACT) {
     PPD_TRY(degrid_dual(p, c.dual, p->part));               // step 10 argument w
-    PPD_TRY(secular_solve(p, p->wbuf, c.dual.y, c.dual.U, c.n_newton));   // exact prox^U_h(w)
+    PPD_TRY(secular_solve(p, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.n_newton));   // exact prox^U_h(w)
     PPD_TRY(grid_dual_exact(p, c.dual));                    // steps 10-12
   } else if (c.form == PPD_FORM_FUSED) {
     double* pa = p->part;
     double* pb = p->part + p->n_segs;
     PPD_TRY(degrid_dual(p, c.dual, pa));                    // step 10 argument, first Alg. 2 step
     for (int s = 1; s < c.dual.n_itr; ++s) {
-      PPD_TRY(alg2_launch(p, 1, p->wbuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb, c.dual.active));
+      PPD_TRY(alg2_launch(p, 1, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb,
+                          c.dual.active));
       std::swap(pa, pb);
     }
     PPD_TRY(grid_dual(p, c.dual, pa));                      // steps 10-12

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(64 * DEGRID_WAVES) void k_degrid(
     const Seg* __restrict__ segs, const float* __restrict__ wu, const float* __restrict__ wv,
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
     float2* __restrict__ out, const float2* __restrict__ y, const double* __restrict__ U,
-    const float2* __restrict__ v, const double2* __restrict__ z, double2* __restrict__ wout, double mu,
+    const float2* __restrict__ v, const double2* __restrict__ z, float2* __restrict__ gout, double mu,
     double* __restrict__ part, double* __restrict__ rpart) {
   constexpr int R = T + 7;
   constexpr int NW = DEGRID_WAVES;
@@ -162,10 +162,11 @@ __global__ __launch_bounds__(64 * DEGRID_WAVES) void k_degrid(
       if (!DUAL) {
         out[pi] = g;
       } else {
-        // Algorithm 3 step 10: w = U^-1 v + Theta G a; first Algorithm 2 step
-        const double wx = double(ve.x) / Ue + double(g.x);
-        const double wy = double(ve.y) / Ue + double(g.y);
-        wout[pi] = make_double2(wx, wy);
+        // Algorithm 3 step 10: w = U^-1 v + Theta G a (Theta G a kept for the
+        // gridding pass, which rebuilds w); first Algorithm 2 step
+        gout[pi] = g;
+        const double2 we = dual_arg(ve, Ue, g);
+        const double wx = we.x, wy = we.y;
         const double mU = mu * Ue;
         const double dx = (ze.x - mU * (ze.x - wx)) - double(ye.x);
         const double dy = (ze.y - mU * (ze.y - wy)) - double(ye.y);
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     const Seg* __restrict__ segs, const float* __restrict__ wu, const float* __restrict__ wv,
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
     const float2* __restrict__ vin, const float2* __restrict__ y, const double* __restrict__ U,
-    float2* __restrict__ v, double2* __restrict__ z, const double2* __restrict__ w, double mu,
+    float2* __restrict__ v, double2* __restrict__ z, const float2* __restrict__ ga, double mu,
     double lambda, const double2* __restrict__ bfac, int exact, const uint8_t* __restrict__ active) {
   constexpr int R = GridCfg<T>::R;
   constexpr int RS = GridCfg<T>::RS;
@@ -260,8 +261,8 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
   // their latency overlaps the LDS work.
   struct Batch {
     float ou, ov, th;
-    float2 vin, y, v;
-    double2 w, z, bf;
+    float2 vin, y, v, ga;
+    double2 z, bf;
     double U;
     int pi;
     bool act;
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
       if (!DUAL) {
         b.vin = vin[pi];
       } else {
-        b.w = w[pi];
+        b.ga = ga[pi];
         b.z = z[pi];
         b.U = U[pi];
         b.y = y[pi];
@@ -317,22 +318,23 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
       } else {
         // last Algorithm 2 projection z = P_B(q) with the block's factor,
         // then steps 10-11
+        const double2 bw = dual_arg(bt.v, bt.U, bt.ga);   // w of step 10
         double zx, zy;
         if (exact) {
           // exact prox: (U w + nu y) / (U + nu) with the block's nu, w if nu = 0
           const double nu = bt.bf.x, inv = 1.0 / (bt.U + nu);
-          zx = nu == 0.0 ? bt.w.x : (bt.U * bt.w.x + nu * double(bt.y.x)) * inv;
-          zy = nu == 0.0 ? bt.w.y : (bt.U * bt.w.y + nu * double(bt.y.y)) * inv;
+          zx = nu == 0.0 ? bw.x : (bt.U * bw.x + nu * double(bt.y.x)) * inv;
+          zy = nu == 0.0 ? bw.y : (bt.U * bw.y + nu * double(bt.y.y)) * inv;
         } else {
           const double fac = bt.bf.x;
           const bool inside = bt.bf.y != 0.0;
           const double mU = mu * bt.U;
-          const double qx = bt.z.x - mU * (bt.z.x - bt.w.x), qy = bt.z.y - mU * (bt.z.y - bt.w.y);
+          const double qx = bt.z.x - mU * (bt.z.x - bw.x), qy = bt.z.y - mU * (bt.z.y - bw.y);
           zx = inside ? qx : double(bt.y.x) + (qx - double(bt.y.x)) * fac;
           zy = inside ? qy : double(bt.y.y) + (qy - double(bt.y.y)) * fac;
         }
         znew = make_double2(zx, zy);
-        const double vbx = bt.U * (bt.w.x - zx), vby = bt.U * (bt.w.y - zy);
+        const double vbx = bt.U * (bw.x - zx), vby = bt.U * (bw.y - zy);
         const float2 vn = make_float2(float(double(bt.v.x) + lambda * (vbx - double(bt.v.x))),
                                       float(double(bt.v.y) + lambda * (vby - double(bt.v.y))));
         vnew = vn;
@@ -468,7 +470,7 @@ int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double
   } else {
     hipLaunchKernelGGL((k_degrid<T, true>), dim3(p->n_launch), dim3(64 * DEGRID_WAVES), 0, p->stream, p->grid_f,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
-                       p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->wbuf, a->mu,
+                       p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->gabuf, a->mu,
                        part_out, p->rpart);
   }
   PPD_HIP(hipGetLastError());
@@ -485,7 +487,7 @@ int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, in
   } else {
     hipLaunchKernelGGL((k_grid<T, true>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
-                       p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->wbuf, a->mu,
+                       p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->gabuf, a->mu,
                        a->lambda, p->bfac, exact, a->active);
   }
   PPD_HIP(hipGetLastError());

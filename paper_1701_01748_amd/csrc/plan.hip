@@ -449,6 +449,7 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   A(dalloc(p, &p->half, size_t(p->ny) * p->Kx));
   A(dalloc(p, &p->ybuf, M));
   A(dalloc(p, &p->wbuf, M));
+  A(dalloc(p, &p->gabuf, M));
   A(dalloc(p, &p->qbuf, M));
   A(dalloc(p, &p->part, 2 * size_t(p->n_segs)));
   A(dalloc(p, &p->rpart, p->n_segs));

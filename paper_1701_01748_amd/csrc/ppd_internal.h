@@ -110,7 +110,8 @@ struct ppd_plan {
   float2* grid_a = nullptr;                // adjoint accumulation Ky x Kx
   float2* half = nullptr;                  // ny x Kx intermediate
   float2* ybuf = nullptr;                  // [M] complex64 scratch
-  double2* wbuf = nullptr;                 // [M] complex128 w (dual prologue)
+  double2* wbuf = nullptr;                 // [M] complex128 w (plain form)
+  float2* gabuf = nullptr;                 // [M] complex64 Theta G a (fused form; w is rebuilt from it)
   double2* qbuf = nullptr;                 // [M] complex128 (plain form)
   double* part = nullptr;                  // [2][n_segs] block-norm partials
   double* rpart = nullptr;                 // [n_segs] residual partials
@@ -170,7 +171,7 @@ struct DualArgs {
   int n_itr;
   const uint8_t* active;   // DEVICE [d] block mask of this iteration, NULL = all
 };
-int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out);   // grid_f -> wbuf
+int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out);   // grid_f -> gabuf
 int grid_plain(ppd_plan* p, const float2* v);                 // v -> grid_a (accumulate)
 int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in);  // dual finish + grid
 
@@ -179,7 +180,9 @@ int plain_dual(ppd_plan* p, const DualArgs& a);               // per-block unfus
 // ||q - y||^2: bfac[j] = (min(1, eps_j / r_j), r_j <= eps_j), r_j the block norm.
 int block_factors(ppd_plan* p, const double* part);
 // n_newton Newton steps of the exact prox per block; nu_j in bfac[j].x.
-int secular_solve(ppd_plan* p, const double2* w, const float2* y, const double* U, int n_newton);
+// The prox argument is w if non-NULL, else U^-1 v + ga (see dual_arg).
+int secular_solve(ppd_plan* p, const double2* w, const float2* v, const float2* ga, const float2* y,
+                  const double* U, int n_newton);
 int grid_dual_exact(ppd_plan* p, const DualArgs& a);   // dual finish with the exact prox + grid
 int permute(ppd_plan* p, int direction, const void* in, void* out, int elem_bytes);
 
@@ -224,6 +227,13 @@ __host__ __device__ inline void kb_weights(float s, const float* __restrict__ c,
   }
 }
 static_assert(KB_DEG % 2 == 1, "even / odd split assumes an odd degree");
+
+// Algorithm 3 step 10 argument w = U^-1 v + Theta G a in FP64; the fused form
+// stores Theta G a (complex64) and rebuilds w where it is needed, bitwise
+// the same each time.
+__device__ __forceinline__ double2 dual_arg(float2 v, double U, float2 ga) {
+  return make_double2(double(v.x) / U + double(ga.x), double(v.y) / U + double(ga.y));
+}
 
 // Segment table of a work item in LDS: the offsets of its segments in the
 // item's flattened visibility range (pre[n] = total), their first visibility
