@@ -133,42 +133,45 @@ struct OnStream {
   ~OnStream() { p->stream = saved; }
 };
 
-// One iteration of Algorithm 3 (no randomisation) on the plan's stream.
-// Steps 19-21 (SARA dual update and synthesis) need only x~ and u, so they
-// are forked to the plan's second stream and run concurrently with the
-// data-fidelity path (steps 4-12); the primal update (steps 28-30) waits for
-// both.  Under graph capture the fork and join become edges of the graph.
+// One iteration of Algorithm 3 on the plan's stream.  Steps 19-21 (SARA
+// dual update and synthesis) need only x~ and u, so the data-fidelity path
+// (steps 4-12 and the inverse FFT of step 28) is forked to the plan's second
+// stream and runs concurrently with them; the primal update (steps 28-30)
+// waits for both on the plan's stream.  Under graph capture the fork and
+// join become graph edges.  (Forking SARA instead and keeping the data path
+// on the plan's stream measured ~10 us slower per replayed iteration: the
+// join then moved the critical path across hardware queues twice.)
 int one_iteration(ppd_plan* p, const IterCtx& c) {
   const float* xt = c.primal.xt;
   PPD_HIP(hipEventRecord(p->ev_fork, p->stream));
   PPD_HIP(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
   {
     OnStream on(p, p->aux);
-    PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda, c.W, c.basis_active));   // steps 19-20
-    PPD_TRY(sara_synthesis(p, c.u, p->ut, c.W));              // step 21, summed over i
+    PPD_TRY(fft_forward(p, xt));                              // step 4: a = F Z x~
+    if (c.form == PPD_FORM_FUSED && c.prox == PPD_PROX_EXACT) {
+      PPD_TRY(degrid_dual(p, c.dual, p->part));               // step 10 argument w
+      PPD_TRY(secular_solve(p, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.n_newton));  // prox^U_h(w)
+      PPD_TRY(grid_dual_exact(p, c.dual));                    // steps 10-12
+    } else if (c.form == PPD_FORM_FUSED) {
+      double* pa = p->part;
+      double* pb = p->part + p->n_segs;
+      PPD_TRY(degrid_dual(p, c.dual, pa));                    // step 10 argument, first Alg. 2 step
+      for (int s = 1; s < c.dual.n_itr; ++s) {
+        PPD_TRY(alg2_launch(p, 1, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb,
+                            c.dual.active));
+        std::swap(pa, pb);
+      }
+      PPD_TRY(grid_dual(p, c.dual, pa));                      // steps 10-12
+    } else {
+      PPD_TRY(degrid_plain(p, p->ybuf));
+      PPD_TRY(plain_dual(p, c.dual));                         // steps 10-11, block by block
+      PPD_TRY(grid_plain(p, c.dual.v));                       // step 12
+    }
+    PPD_TRY(fft_cols_inverse(p));
     PPD_HIP(hipEventRecord(p->ev_join, p->aux));
   }
-  PPD_TRY(fft_forward(p, xt));                              // step 4: a = F Z x~
-  if (c.form == PPD_FORM_FUSED && c.prox == PPD_PROX_EXACT) {
-    PPD_TRY(degrid_dual(p, c.dual, p->part));               // step 10 argument w
-    PPD_TRY(secular_solve(p, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.n_newton));   // exact prox^U_h(w)
-    PPD_TRY(grid_dual_exact(p, c.dual));                    // steps 10-12
-  } else if (c.form == PPD_FORM_FUSED) {
-    double* pa = p->part;
-    double* pb = p->part + p->n_segs;
-    PPD_TRY(degrid_dual(p, c.dual, pa));                    // step 10 argument, first Alg. 2 step
-    for (int s = 1; s < c.dual.n_itr; ++s) {
-      PPD_TRY(alg2_launch(p, 1, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb,
-                          c.dual.active));
-      std::swap(pa, pb);
-    }
-    PPD_TRY(grid_dual(p, c.dual, pa));                      // steps 10-12
-  } else {
-    PPD_TRY(degrid_plain(p, p->ybuf));
-    PPD_TRY(plain_dual(p, c.dual));                         // steps 10-11, block by block
-    PPD_TRY(grid_plain(p, c.dual.v));                       // step 12
-  }
-  PPD_TRY(fft_cols_inverse(p));
+  PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda, c.W, c.basis_active));   // steps 19-20
+  PPD_TRY(sara_synthesis(p, c.u, p->ut, c.W));              // step 21, summed over i
   PPD_HIP(hipStreamWaitEvent(p->stream, p->ev_join, 0));
   return fft_rows_inverse_primal(p, c.primal);              // steps 28-30
 }
