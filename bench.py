@@ -35,9 +35,12 @@ KIND_SOURCE = {"degrid": "nufft.hip", "grid": "nufft.hip", "fold": "nufft.hip",
 
 
 def source_sha(name: str) -> str:
+    """Hash of a kernel source's code lines (comments and blank lines
+    dropped, so that editing a comment keeps the recorded counters valid)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1701_01748_amd", "csrc", name), "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()[:12]
+    with open(os.path.join(ROOT, "paper_1701_01748_amd", "csrc", name)) as f:
+        code = [ln.split("//", 1)[0].rstrip() for ln in f]
+    return hashlib.sha1("\n".join(ln for ln in code if ln).encode()).hexdigest()[:12]
 
 
 def measured_traffic(kind: str, workload: str, tile: int, chunk: int):

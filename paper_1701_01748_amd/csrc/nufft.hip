@@ -7,17 +7,18 @@
 // its 7-cell halo, (T+7)^2 complex cells, in LDS:
 //   degrid: the forward spectrum region is copied in, each thread then
 //           interpolates its visibilities from LDS (64 taps each);
-//   grid:   each wave owns a private copy of the region; a batch of 64
+//   grid:   each wave owns private copies of the region; a batch of 64
 //           visibilities is prepared one per lane (weights to LDS), then
 //           applied one visibility at a time with lane (a, b) owning tap
 //           (a, b), so a wave's 64 read-modify-writes never collide and no
-//           atomics are needed.  The wave copies are summed and stored to a
+//           atomics are needed.  The copies are summed and stored to a
 //           per-item scratch slot; a fold pass then sums, for
 //           every grid cell, the slots of the owning tile and the halos of
 //           its left / upper / upper-left neighbours.  No global atomics,
 //           no zeroing pass, and a fixed summation order across items.
-// The 8 per-axis weights are evaluated on the fly from degree-9
-// polynomials, so only the two float32 frequencies are read per visibility.
+// The 8 per-axis weights are evaluated on the fly from the even and odd
+// parts of four degree-9 polynomials (the kernel is even), so only the two
+// float32 frequencies are read per visibility.
 // Items are launched in spatial order through an XCD-aware remap.
 #include "ppd_internal.h"
 
