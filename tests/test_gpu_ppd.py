@@ -119,3 +119,30 @@ def test_workload64_snr_parity():
             snr.append(s["snr_db"])
             assert abs(s["snr_db"] - h[10 * k + 9]["snr"]) < 0.05, (name, k, s["snr_db"], h[10 * k + 9]["snr"])
         assert rel_err(host(st.x), ost.x) < 1e-3
+
+
+def test_many_blocks_per_tile():
+    """100 blocks spread over the whole u-v plane (each tile holds points of
+    every block): work items are cut at 64 segments, and both the operators
+    and the iteration still match the oracle."""
+    P = require_gpu()
+    import torch
+    from oracle import nufft as onf
+    announce("100 interleaved blocks")
+    n, M, d = 32, 20000, 100
+    x, wu, wv, _ = synth.small_case(n, M, seed=14, coverage="uniform")
+    off = np.linspace(0, M, d + 1).astype(np.int64)
+    pb = oprob.make_problem(x, wu, wv, off, synth.noise_unit(M, 214), 30.0, np.ones((n, n)), power_tol=1e-8)
+    plan = P.Plan(n, n, wu, wv, off)
+    info = plan.info
+    assert info.n_chunks > (2 * n // info.tile) ** 2          # tiles split by the segment cap
+    perm, y, U = _gpu_inputs(P, plan, pb)
+    yg = P.ppd_phi(plan, dev(x.astype(np.float32), torch.float32))
+    assert_op_close(host(yg), pb.op.phi(x.astype(np.float32).astype(np.float64))[perm], what="phi")
+    st = P.PPDState(plan, y)
+    ost = O.init_state(n, n, pb.y)
+    prm = O.Params(eta=pb.eta, mu=1.0, n_itr=2)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, ost, 3)
+    P.ppd_iterate(plan, st, y, U, pb.eps, 3, eta=pb.eta, mu=1.0, n_itr=2)
+    assert_op_close(host(st.x), ost.x, what="x")
+    assert_op_close(host(st.z), ost.z[perm], what="z")
