@@ -69,7 +69,9 @@ typedef struct {
   int32_t levels;             /* SARA decomposition levels (1..6), 0 -> 3       */
   int32_t tile;               /* gridding tile edge in grid cells: 16, 32 or 64;
                                  0 -> 16                                         */
-  int32_t chunk;              /* max visibilities per work chunk, 0 -> 512      */
+  int32_t chunk;              /* max visibilities per work chunk (64..65536),
+                                 0 -> 512; a chunk also holds at most 64 data
+                                 blocks' segments of its tile                   */
 } ppd_plan_desc;
 
 /* Create a plan: validates desc, bins the visibilities by (block, tile) on
@@ -199,7 +201,10 @@ typedef struct {
   double mu;                       /* Algorithm 2 step, <= 1 / max U          */
   int32_t n_itr;                   /* Algorithm 2 iterations (>= 1)           */
   int32_t form;                    /* PPD_FORM_*                              */
-  int32_t use_graph;               /* replay one captured iteration as a HIP graph */
+  int32_t use_graph;               /* replay one captured iteration as a HIP
+                                      graph (needs a non-default plan stream);
+                                      re-captured when a pointer or scalar of
+                                      these params or the state changes      */
   int32_t pad_;
   const float* y;                  /* [M] complex64 data, plan order          */
   const double* U;                 /* [M] float64 preconditioner, plan order  */
@@ -227,8 +232,11 @@ typedef struct {
   double residual_max;   /* max_j ||Theta_j G_j F Z x~_{t-1} - y_j|| / eps_j  */
 } ppd_stats;
 
-/* Run n_iter iterations of Algorithm 3 (no randomisation: every block and
- * basis is updated each iteration) on `state`.  Step 10 is read as
+/* Run n_iter iterations of Algorithm 3 on `state`.  Every block and basis
+ * is updated each iteration unless params->block_active / basis_active name
+ * active subsets (the randomised variant; the masks are read on the device
+ * at each iteration, so the caller may rewrite them between calls).
+ * Step 10 is read as
  * vbar_j = U_j (w_j - prox^U_h(w_j)), w_j = U_j^{-1} v_j + Theta_j G_j a,
  * with the prox approximated by n_itr Algorithm 2 iterations warm-started
  * from state->z (PPD_PROX_FB), or computed as by ppd_prox_metric
