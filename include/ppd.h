@@ -67,11 +67,12 @@ typedef struct {
   double kb_beta;             /* Kaiser-Bessel shape; <= 0 selects the default
                                  pi sqrt(35.2) (width 8, 2x oversampling)        */
   int32_t levels;             /* SARA decomposition levels (1..6), 0 -> 3       */
-  int32_t tile;               /* gridding tile edge in grid cells: 16, 32 or 64;
-                                 0 -> 16                                         */
+  int32_t tile;               /* gridding tile edge in grid cells: 8, 16, 32 or
+                                 64 (8: gridding on the matrix cores); 0 -> 8    */
   int32_t chunk;              /* max visibilities per work chunk (64..65536),
-                                 0 -> 512; a chunk also holds at most 64 data
-                                 blocks' segments of its tile                   */
+                                 0 -> 128 for tile 8, else 512; a chunk also
+                                 holds at most 64 data blocks' segments of its
+                                 tile                                            */
 } ppd_plan_desc;
 
 /* Create a plan: validates desc, bins the visibilities by (block, tile) on

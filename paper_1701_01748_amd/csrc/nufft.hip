@@ -7,15 +7,18 @@
 // its 7-cell halo, (T+7)^2 complex cells, in LDS:
 //   degrid: the forward spectrum region is copied in, each thread then
 //           interpolates its visibilities from LDS (64 taps each);
-//   grid:   each wave owns private copies of the region; a batch of 64
-//           visibilities is prepared one per lane (weights to LDS), then
-//           applied one visibility at a time with lane (a, b) owning tap
-//           (a, b), so a wave's 64 read-modify-writes never collide and no
-//           atomics are needed.  The copies are summed and stored to a
-//           per-item scratch slot; a fold pass then sums, for
-//           every grid cell, the slots of the owning tile and the halos of
-//           its left / upper / upper-left neighbours.  No global atomics,
-//           no zeroing pass, and a fixed summation order across items.
+//   grid:   8 x 8 tiles (the default): the region is one 16 x 16 matrix
+//           tile and gridding a product of the separable weights, done on
+//           the matrix cores (k_grid_mfma).  Larger tiles: each wave owns
+//           private copies of the region; a batch of 64 visibilities is
+//           prepared one per lane (weights to LDS), then applied one
+//           visibility at a time with lane (a, b) owning tap (a, b), so a
+//           wave's 64 read-modify-writes never collide and no atomics are
+//           needed (k_grid).  Either way the item's region is stored to a
+//           per-item scratch slot; a fold pass then sums, for every grid
+//           cell, the slots of the owning tile and the halos of its left /
+//           upper / upper-left neighbours.  No global atomics, no zeroing
+//           pass, and a fixed summation order across items.
 // The 8 per-axis weights are evaluated on the fly from the even and odd
 // parts of four degree-9 polynomials (the kernel is even), so only the two
 // float32 frequencies are read per visibility.
@@ -44,7 +47,18 @@ __device__ __forceinline__ void taps_for(float omu, float omv, double su, double
   kb_weights(float(tv - fv), coef, t.wy);
 }
 
-constexpr int DEGRID_WAVES = 4;
+#ifndef PPD_DEGRID_WAVES
+#define PPD_DEGRID_WAVES 4
+#endif
+#ifndef PPD_DEGRID_WAVES8
+#define PPD_DEGRID_WAVES8 1
+#endif
+// Waves per degridding workgroup: 8 x 8 tiles hold ~100 visibilities, one
+// wave's worth, so there each item is one single-wave workgroup.
+template <int T>
+struct DegridCfg {
+  static constexpr int NW = T == 8 ? PPD_DEGRID_WAVES8 : PPD_DEGRID_WAVES;
+};
 
 // Degridding: one workgroup per item, the region staged in LDS; the item's
 // visibilities (all its segments, flattened) are taken in batches of 64, a
@@ -53,7 +67,7 @@ constexpr int DEGRID_WAVES = 4;
 // the lanes of each segment, added per wave in batch order and summed over
 // the waves in a fixed order at the end: deterministic.
 template <int T, bool DUAL>
-__global__ __launch_bounds__(64 * DEGRID_WAVES) void k_degrid(
+__global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
     const float2* __restrict__ grid, int Kx, int Ky, const Item* __restrict__ items, int n_items,
     const Seg* __restrict__ segs, const float* __restrict__ wu, const float* __restrict__ wv,
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
@@ -61,7 +75,7 @@ __global__ __launch_bounds__(64 * DEGRID_WAVES) void k_degrid(
     const float2* __restrict__ v, const double2* __restrict__ z, float2* __restrict__ gout, double mu,
     double* __restrict__ part, double* __restrict__ rpart) {
   constexpr int R = T + 7;
-  constexpr int NW = DEGRID_WAVES;
+  constexpr int NW = DegridCfg<T>::NW;
   __shared__ float2 reg[R * R];
   __shared__ float coef[KB_TAPS * KB_NC];
   __shared__ ItemTab tab;
@@ -203,6 +217,82 @@ __global__ __launch_bounds__(64 * DEGRID_WAVES) void k_degrid(
   }
 }
 
+// Operands of one gridding batch (one visibility per lane), loaded a batch
+// ahead of use.
+struct GridBatch {
+  float ou, ov, th;
+  float2 vin, y, v, ga;
+  double2 z, bf;
+  double U;
+  int pi;
+  bool act;
+};
+
+struct GridSrc {
+  const float* wu; const float* wv; const float* theta;
+  const float2* vin; const float2* y; const double* U; const float2* v; const double2* z;
+  const float2* ga; const double2* bfac; const uint8_t* active;
+};
+
+// Loads batch bt (64 flattened visibilities of the item) for this lane;
+// sb tracks the segment of the batch's first visibility.
+template <bool DUAL>
+__device__ __forceinline__ void grid_load(const GridSrc& g, const ItemTab& tab, int total, int lane, int bt,
+                                          int& sb, GridBatch& b) {
+  while (bt * 64 >= tab.pre[sb + 1]) ++sb;
+  const int li = bt * 64 + lane;
+  if (li < total) {
+    const int sg = seg_of(li, sb, tab.pre);
+    const int pi = tab.start[sg] + (li - tab.pre[sg]);
+    b.pi = pi;
+    b.ou = g.wu[pi];
+    b.ov = g.wv[pi];
+    b.th = g.theta ? g.theta[pi] : 1.0f;
+    if (!DUAL) {
+      b.vin = g.vin[pi];
+    } else {
+      b.ga = g.ga[pi];
+      b.z = g.z[pi];
+      b.U = g.U[pi];
+      b.y = g.y[pi];
+      b.v = g.v[pi];
+      b.bf = g.bfac[tab.block[sg]];
+      b.act = !g.active || g.active[tab.block[sg]];
+    }
+  }
+}
+
+// The value a visibility spreads onto the grid (before Theta).  In the dual
+// mode: the last Algorithm 2 projection z = P_B(q) with the block's factor
+// (or the exact prox with the block's nu), then steps 10-11; an inactive
+// block (randomised updates, steps 14-17) keeps v and z and spreads its v.
+template <bool DUAL>
+__device__ __forceinline__ float2 grid_value(const GridBatch& bt, double mu, double lambda, int exact,
+                                             double2& znew, float2& vnew) {
+  if (!DUAL) return bt.vin;
+  if (!bt.act) return bt.v;
+  const double2 bw = dual_arg(bt.v, bt.U, bt.ga);   // w of step 10
+  double zx, zy;
+  if (exact) {
+    // exact prox: (U w + nu y) / (U + nu) with the block's nu, w if nu = 0
+    const double nu = bt.bf.x, inv = 1.0 / (bt.U + nu);
+    zx = nu == 0.0 ? bw.x : (bt.U * bw.x + nu * double(bt.y.x)) * inv;
+    zy = nu == 0.0 ? bw.y : (bt.U * bw.y + nu * double(bt.y.y)) * inv;
+  } else {
+    const double fac = bt.bf.x;
+    const bool inside = bt.bf.y != 0.0;
+    const double mU = mu * bt.U;
+    const double qx = bt.z.x - mU * (bt.z.x - bw.x), qy = bt.z.y - mU * (bt.z.y - bw.y);
+    zx = inside ? qx : double(bt.y.x) + (qx - double(bt.y.x)) * fac;
+    zy = inside ? qy : double(bt.y.y) + (qy - double(bt.y.y)) * fac;
+  }
+  znew = make_double2(zx, zy);
+  const double vbx = bt.U * (bw.x - zx), vby = bt.U * (bw.y - zy);
+  vnew = make_float2(float(double(bt.v.x) + lambda * (vbx - double(bt.v.x))),
+                     float(double(bt.v.y) + lambda * (vby - double(bt.v.y))));
+  return vnew;
+}
+
 // Gridding workgroup shape: NW waves, each owning C private copies of the
 // (T+7)^2 region in LDS (rows padded to T+8 cells, so the 8 tap rows of a
 // footprint fall in distinct LDS banks).  Visibility k of a batch goes to
@@ -260,45 +350,15 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
   // of 64, batch k by wave k mod NW.  The global operands of a wave's next
   // batch are loaded before its current batch is prepared and applied, so
   // their latency overlaps the LDS work.
-  struct Batch {
-    float ou, ov, th;
-    float2 vin, y, v, ga;
-    double2 z, bf;
-    double U;
-    int pi;
-    bool act;
-  };
+  const GridSrc src{wu, wv, theta, vin, y, U, v, z, ga, bfac, active};
   const int nseg = it.seg1 - it.seg0;
   const int total = tab.pre[nseg];
-  auto load = [&](int bt, int& sb, Batch& b) {
-    while (bt * 64 >= tab.pre[sb + 1]) ++sb;
-    const int li = bt * 64 + lane;
-    if (li < total) {
-      const int sg = seg_of(li, sb, tab.pre);
-      const int pi = tab.start[sg] + (li - tab.pre[sg]);
-      b.pi = pi;
-      b.ou = wu[pi];
-      b.ov = wv[pi];
-      b.th = theta ? theta[pi] : 1.0f;
-      if (!DUAL) {
-        b.vin = vin[pi];
-      } else {
-        b.ga = ga[pi];
-        b.z = z[pi];
-        b.U = U[pi];
-        b.y = y[pi];
-        b.v = v[pi];
-        b.bf = bfac[tab.block[sg]];
-        b.act = !active || active[tab.block[sg]];
-      }
-    }
-  };
   int sb = 0;
-  Batch bn{};
-  if (uwid * 64 < total) load(uwid, sb, bn);
+  GridBatch bn{};
+  if (uwid * 64 < total) grid_load<DUAL>(src, tab, total, lane, uwid, sb, bn);
   for (int k = uwid; k * 64 < total; k += NW) {
-    const Batch bt = bn;
-    if ((k + NW) * 64 < total) load(k + NW, sb, bn);
+    const GridBatch bt = bn;
+    if ((k + NW) * 64 < total) grid_load<DUAL>(src, tab, total, lane, k + NW, sb, bn);
     const int nb = min(64, total - k * 64);
     // prepare: one visibility per lane (lanes past nb carry zero weight).
     // The new z and v are stored after the apply loop, so that no store is
@@ -310,37 +370,7 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     Taps t;
     if (lane < nb) {
       taps_for<T>(bt.ou, bt.ov, su, sv, Kx, Ky, c0, r0, coef, t);
-      float2 val;
-      if (!DUAL) {
-        val = bt.vin;
-      } else if (!bt.act) {
-        // randomised updates (steps 14-17): an inactive block keeps v and z
-        val = bt.v;
-      } else {
-        // last Algorithm 2 projection z = P_B(q) with the block's factor,
-        // then steps 10-11
-        const double2 bw = dual_arg(bt.v, bt.U, bt.ga);   // w of step 10
-        double zx, zy;
-        if (exact) {
-          // exact prox: (U w + nu y) / (U + nu) with the block's nu, w if nu = 0
-          const double nu = bt.bf.x, inv = 1.0 / (bt.U + nu);
-          zx = nu == 0.0 ? bw.x : (bt.U * bw.x + nu * double(bt.y.x)) * inv;
-          zy = nu == 0.0 ? bw.y : (bt.U * bw.y + nu * double(bt.y.y)) * inv;
-        } else {
-          const double fac = bt.bf.x;
-          const bool inside = bt.bf.y != 0.0;
-          const double mU = mu * bt.U;
-          const double qx = bt.z.x - mU * (bt.z.x - bw.x), qy = bt.z.y - mU * (bt.z.y - bw.y);
-          zx = inside ? qx : double(bt.y.x) + (qx - double(bt.y.x)) * fac;
-          zy = inside ? qy : double(bt.y.y) + (qy - double(bt.y.y)) * fac;
-        }
-        znew = make_double2(zx, zy);
-        const double vbx = bt.U * (bw.x - zx), vby = bt.U * (bw.y - zy);
-        const float2 vn = make_float2(float(double(bt.v.x) + lambda * (vbx - double(bt.v.x))),
-                                      float(double(bt.v.y) + lambda * (vby - double(bt.v.y))));
-        vnew = vn;
-        val = vn;
-      }
+      const float2 val = grid_value<DUAL>(bt, mu, lambda, exact, znew, vnew);
       vx = val.x * bt.th;
       vy = val.y * bt.th;
       pos = t.ov * RS + t.ou;
@@ -405,6 +435,189 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
   }
 }
 
+// Gridding of 8 x 8 tiles as a matrix product on the matrix cores.  The
+// item's region (15 x 15 cells, padded to 16 x 16) receives
+//     G[i][j] = sum_k wy_k(i) * (wx_k(j) * theta_k * val_k),
+// wy_k(i) the v-axis weight of visibility k at region row i (zero outside
+// its 8 taps), wx_k(j) likewise along u: a 16 x 16 x K product of the
+// separable weights, accumulated over the item's visibilities 4 at a time by
+// v_mfma_f32_16x16x4_f32 (real and imaginary parts), in FP32 registers.  A
+// batch of 64 visibilities is prepared one per lane, as in k_grid, and
+// written to LDS as zero-padded 16-entry weight rows (the A operand) and
+// value-scaled weight rows (B); lane l of a product step then reads row
+// 4 g + l / 16, entry l mod 16, of each.  No read-modify-write of LDS.
+//
+// An 8 x 8 tile holds about one batch, so a single-wave workgroup takes a
+// run of consecutive items, and the wave's (item, batch) steps form one
+// software pipeline: the operands of the next step, which may be the next
+// item's first batch, are loaded before the current step is prepared and
+// applied, and the next item's segment list is fetched into registers when
+// the current item starts.  Only the first step of a run waits for memory.
+#ifndef PPD_GRIDM_RUN
+#define PPD_GRIDM_RUN 2
+#endif
+#ifndef PPD_GRIDM_WPG
+#define PPD_GRIDM_WPG 1
+#endif
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int GM_T = 8;
+constexpr int GM_AS = 17;   // A row stride (floats): spreads the prepare writes over banks
+constexpr int GM_BS = 17;   // B row stride (float2)
+static_assert(PPD_GRIDM_RUN >= 1 && PPD_GRIDM_RUN <= 64, "a run's items are held one per lane");
+
+// The segment list of one item as a lane's register (lane s: segment s).
+__device__ __forceinline__ Seg item_seg(const Seg* __restrict__ segs, int seg0, int seg1, int lane) {
+  Seg sg{0, 0, 0, 0};
+  if (lane < seg1 - seg0) sg = segs[seg0 + lane];
+  return sg;
+}
+
+// Segment table of an item from its lanes' segments (exclusive prefix sum
+// of the counts); wave-local.
+__device__ __forceinline__ void tab_from_seg(const Seg& sg, int lane, ItemTab& tab) {
+  tab.start[lane] = sg.start;
+  tab.block[lane] = sg.block;
+  int inc = sg.count;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  tab.pre[lane + 1] = inc;
+  if (lane == 0) tab.pre[0] = 0;
+}
+
+template <bool DUAL>
+__global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
+    float2* __restrict__ scratch, int Kx, int Ky, const Item* __restrict__ items, int n_items,
+    const Seg* __restrict__ segs, const float* __restrict__ wu, const float* __restrict__ wv,
+    const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
+    const float2* __restrict__ vin, const float2* __restrict__ y, const double* __restrict__ U,
+    float2* __restrict__ v, double2* __restrict__ z, const float2* __restrict__ ga, double mu,
+    double lambda, const double2* __restrict__ bfac, int exact, const uint8_t* __restrict__ active) {
+  constexpr int T = GM_T, R = T + 7, WPG = PPD_GRIDM_WPG;
+  static_assert(R <= 16, "the region must fit one 16 x 16 product tile");
+  __shared__ float sAw[WPG][64 * GM_AS];
+  __shared__ float2 sBw[WPG][64 * GM_BS];
+  __shared__ float coef[KB_TAPS * KB_NC];
+  __shared__ ItemTab tabsw[WPG][2];   // per wave: current and next item
+  for (int i = threadIdx.x; i < KB_TAPS * KB_NC; i += blockDim.x) coef[i] = kbc[i];
+  __syncthreads();
+  // each wave of the workgroup works alone from here on
+  const int wid = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int i0 = (xcd_remap(blockIdx.x, gridDim.x) * WPG + wid) * PPD_GRIDM_RUN;
+  if (i0 >= n_items) return;
+  const int i1 = min(i0 + PPD_GRIDM_RUN, n_items);
+  const int lane = threadIdx.x & 63;
+  float* sA = sAw[wid];
+  float2* sB = sBw[wid];
+  ItemTab* tabs = tabsw[wid];
+  const int gq = lane >> 4, gc = lane & 15;   // row-in-group and entry read in a product step
+  // the run's items, one per lane; item i's fields come from lane i - i0
+  Item itl{0, 0, 0, 0};
+  if (i0 + lane < i1) itl = items[i0 + lane];
+  const GridSrc src{wu, wv, theta, vin, y, U, v, z, ga, bfac, active};
+  auto field = [&](int v, int i) { return __builtin_amdgcn_readlane(v, i - i0); };
+  tab_from_seg(item_seg(segs, field(itl.seg0, i0), field(itl.seg1, i0), lane), lane, tabs[0]);
+  Seg sgn{0, 0, 0, 0};   // next item's segments, fetched when an item starts
+  if (i0 + 1 < i1) sgn = item_seg(segs, field(itl.seg0, i0 + 1), field(itl.seg1, i0 + 1), lane);
+  __builtin_amdgcn_wave_barrier();
+  f32x4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+  f32x4 accr2 = {0.f, 0.f, 0.f, 0.f}, acci2 = {0.f, 0.f, 0.f, 0.f};
+  int cur = i0, kb = 0, sb = 0;
+  int total = __builtin_amdgcn_readfirstlane(tabs[0].pre[field(itl.seg1, i0) - field(itl.seg0, i0)]);
+  GridBatch bn{};
+  grid_load<DUAL>(src, tabs[0], total, lane, 0, sb, bn);
+  float* arow = sA + lane * GM_AS;
+  float2* brow = sB + lane * GM_BS;
+  while (true) {
+    const GridBatch bt = bn;
+    const int nb = min(64, total - kb * 64);
+    const int c0 = field(itl.tx, cur) * T, r0 = field(itl.ty, cur) * T;
+    // the next step: the next batch of this item, else the next item's first
+    const bool last = (kb + 1) * 64 >= total;
+    const int nxt = last ? cur + 1 : cur;
+    int ntotal = total;
+    if (nxt < i1) {
+      ItemTab& tn = tabs[(nxt - i0) & 1];
+      if (last) {
+        tab_from_seg(sgn, lane, tn);
+        __builtin_amdgcn_wave_barrier();
+        ntotal = __builtin_amdgcn_readfirstlane(tn.pre[field(itl.seg1, nxt) - field(itl.seg0, nxt)]);
+        sb = 0;
+        if (nxt + 1 < i1) sgn = item_seg(segs, field(itl.seg0, nxt + 1), field(itl.seg1, nxt + 1), lane);
+      }
+      grid_load<DUAL>(src, tn, ntotal, lane, last ? 0 : kb + 1, sb, bn);
+    }
+    double2 znew{};
+    float2 vnew{};
+    float vx = 0.f, vy = 0.f;
+    Taps t;
+    if (lane < nb) {
+      taps_for<T>(bt.ou, bt.ov, su, sv, Kx, Ky, c0, r0, coef, t);
+      const float2 val = grid_value<DUAL>(bt, mu, lambda, exact, znew, vnew);
+      vx = val.x * bt.th;
+      vy = val.y * bt.th;
+    } else {
+      // rows past the batch end are read by its last product step: all zero
+      t.ou = 0;
+      t.ov = 0;
+#pragma unroll
+      for (int m = 0; m < KB_TAPS; ++m) {
+        t.wx[m] = 0.f;
+        t.wy[m] = 0.f;
+      }
+    }
+    // the 8 taps at the footprint offset and zeros in the 8 other entries
+#pragma unroll
+    for (int m = 0; m < KB_TAPS; ++m) {
+      arow[t.ov + m] = t.wy[m];
+      arow[(t.ov + KB_TAPS + m) & 15] = 0.f;
+      brow[t.ou + m] = make_float2(t.wx[m] * vx, t.wx[m] * vy);
+      brow[(t.ou + KB_TAPS + m) & 15] = make_float2(0.f, 0.f);
+    }
+    __builtin_amdgcn_wave_barrier();
+    // two accumulator pairs (even / odd product steps): independent chains
+    const int ng = (nb + 3) >> 2;
+    int g = 0;
+    for (; g + 2 <= ng; g += 2) {
+      const int ra = 4 * g + gq, rb = ra + 4;
+      const float a0 = sA[ra * GM_AS + gc], a1 = sA[rb * GM_AS + gc];
+      const float2 b0 = sB[ra * GM_BS + gc], b1 = sB[rb * GM_BS + gc];
+      accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.x, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.y, acci, 0, 0, 0);
+      accr2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1.x, accr2, 0, 0, 0);
+      acci2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1.y, acci2, 0, 0, 0);
+    }
+    if (g < ng) {
+      const int ra = 4 * g + gq;
+      const float a0 = sA[ra * GM_AS + gc];
+      const float2 b0 = sB[ra * GM_BS + gc];
+      accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.x, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.y, acci, 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (DUAL && lane < nb && bt.act) {
+      z[bt.pi] = znew;
+      v[bt.pi] = vnew;
+    }
+    if (last) {
+      // Lane l holds rows 4 (l / 16) + e, e = 0..3, of column l mod 16 (row
+      // 15 and column 15 stay zero: no footprint reaches them).
+      const f32x4 sr = accr + accr2, si = acci + acci2;
+      float2* dst = scratch + size_t(cur) * (R * R);
+      if (gc < R)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (4 * gq + e < R) dst[(4 * gq + e) * R + gc] = make_float2(sr[e], si[e]);
+      accr = accr2 = acci = acci2 = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (nxt >= i1) break;
+    cur = nxt;
+    kb = last ? 0 : kb + 1;
+    total = ntotal;
+  }
+}
+
 // One thread per grid cell (FOLD_CELLS cells per workgroup, T*T/FOLD_CELLS
 // workgroups per tile); the item loops are unrolled so their independent
 // loads overlap.
@@ -434,6 +647,7 @@ __global__ __launch_bounds__(FOLD_CELLS) void k_fold(const float2* __restrict__ 
                                                      int tiles_y, int Kx, float2* __restrict__ grid) {
   constexpr int R = T + 7;
   constexpr int PARTS = (T * T) / FOLD_CELLS;
+  static_assert(PARTS >= 1 && T > 7, "whole workgroups per tile; a cell lies in at most 4 tile regions");
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   if (wg >= tiles_x * tiles_y * PARTS) return;
   const int t = wg / PARTS, part = wg - t * PARTS;
@@ -452,6 +666,66 @@ __global__ __launch_bounds__(FOLD_CELLS) void k_fold(const float2* __restrict__ 
   grid[size_t(ty * T + a) * Kx + (tx * T + b)] = make_float2(sx, sy);
 }
 
+// 8 x 8 tiles: one tile per workgroup, FOLD8_SPLIT threads per cell, thread
+// p taking every FOLD8_SPLIT-th slot from p (a tile's region may come from
+// dozens of items, and their loads are independent); the parts are added in
+// a fixed order.
+#ifndef PPD_FOLD8_SPLIT
+#define PPD_FOLD8_SPLIT 2
+#endif
+constexpr int FOLD8_SPLIT = PPD_FOLD8_SPLIT;
+
+__device__ __forceinline__ void fold_items_strided(const float2* __restrict__ scratch, int R2, int off, int i0,
+                                                   int i1, float& sx, float& sy) {
+  constexpr int S = FOLD8_SPLIT;
+  int i = i0;
+  for (; i + 3 * S < i1; i += 4 * S) {
+    const float2 g0 = scratch[size_t(i) * R2 + off];
+    const float2 g1 = scratch[size_t(i + S) * R2 + off];
+    const float2 g2 = scratch[size_t(i + 2 * S) * R2 + off];
+    const float2 g3 = scratch[size_t(i + 3 * S) * R2 + off];
+    sx += (g0.x + g1.x) + (g2.x + g3.x);
+    sy += (g0.y + g1.y) + (g2.y + g3.y);
+  }
+  for (; i < i1; i += S) {
+    const float2 g = scratch[size_t(i) * R2 + off];
+    sx += g.x;
+    sy += g.y;
+  }
+}
+
+__global__ __launch_bounds__(64 * FOLD8_SPLIT) void k_fold8(const float2* __restrict__ scratch,
+                                                            const int32_t* __restrict__ tio, int tiles_x,
+                                                            int tiles_y, int Kx, float2* __restrict__ grid) {
+  constexpr int T = 8, R = T + 7;
+  __shared__ float2 part[FOLD8_SPLIT][64];
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  if (t >= tiles_x * tiles_y) return;   // uniform over the workgroup
+  const int p = threadIdx.x >> 6, c = threadIdx.x & 63;
+  const int tx = t % tiles_x, ty = t / tiles_x;
+  const int lx = (tx + tiles_x - 1) % tiles_x, uy = (ty + tiles_y - 1) % tiles_y;
+  const int tl = ty * tiles_x + lx, tu = uy * tiles_x + tx, tul = uy * tiles_x + lx;
+  const int a = c / T, b = c - a * T;
+  float sx = 0.f, sy = 0.f;
+  fold_items_strided(scratch, R * R, a * R + b, tio[t] + p, tio[t + 1], sx, sy);
+  if (b < 7) fold_items_strided(scratch, R * R, a * R + T + b, tio[tl] + p, tio[tl + 1], sx, sy);
+  if (a < 7) {
+    fold_items_strided(scratch, R * R, (T + a) * R + b, tio[tu] + p, tio[tu + 1], sx, sy);
+    if (b < 7) fold_items_strided(scratch, R * R, (T + a) * R + T + b, tio[tul] + p, tio[tul + 1], sx, sy);
+  }
+  part[p][c] = make_float2(sx, sy);
+  __syncthreads();
+  if (p == 0) {
+    float2 s = part[0][c];
+#pragma unroll
+    for (int q = 1; q < FOLD8_SPLIT; ++q) {
+      s.x += part[q][c].x;
+      s.y += part[q][c].y;
+    }
+    grid[size_t(ty * T + a) * Kx + (tx * T + b)] = s;
+  }
+}
+
 template <typename E>
 __global__ void k_permute(const int32_t* __restrict__ perm, int64_t M, int to_user,
                           const E* __restrict__ in, E* __restrict__ out) {
@@ -464,15 +738,39 @@ __global__ void k_permute(const int32_t* __restrict__ perm, int64_t M, int to_us
 template <int T>
 int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double* part_out) {
   if (!dual) {
-    hipLaunchKernelGGL((k_degrid<T, false>), dim3(p->n_launch), dim3(64 * DEGRID_WAVES), 0, p->stream, p->grid_f,
+    hipLaunchKernelGGL((k_degrid<T, false>), dim3(p->n_launch), dim3(64 * DegridCfg<T>::NW), 0, p->stream, p->grid_f,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, out, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0,
                        nullptr, nullptr);
   } else {
-    hipLaunchKernelGGL((k_degrid<T, true>), dim3(p->n_launch), dim3(64 * DEGRID_WAVES), 0, p->stream, p->grid_f,
+    hipLaunchKernelGGL((k_degrid<T, true>), dim3(p->n_launch), dim3(64 * DegridCfg<T>::NW), 0, p->stream, p->grid_f,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->gabuf, a->mu,
                        part_out, p->rpart);
+  }
+  PPD_HIP(hipGetLastError());
+  return PPD_OK;
+}
+
+// workgroups of the product gridding: one wave per run of items, a multiple
+// of the XCD count
+int gridm_launch(const ppd_plan* p) {
+  const int runs = (p->n_items + PPD_GRIDM_RUN - 1) / PPD_GRIDM_RUN;
+  const int wgs = (runs + PPD_GRIDM_WPG - 1) / PPD_GRIDM_WPG;
+  return ((wgs + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
+}
+
+int launch_grid_mfma(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, int exact) {
+  if (!dual) {
+    hipLaunchKernelGGL((k_grid_mfma<false>), dim3(gridm_launch(p)), dim3(64 * PPD_GRIDM_WPG), 0, p->stream,
+                       p->gscratch, p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta,
+                       p->su_scale, p->sv_scale, p->kbc, vin, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       0.0, 0.0, nullptr, 0, nullptr);
+  } else {
+    hipLaunchKernelGGL((k_grid_mfma<true>), dim3(gridm_launch(p)), dim3(64 * PPD_GRIDM_WPG), 0, p->stream,
+                       p->gscratch, p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta,
+                       p->su_scale, p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->gabuf, a->mu,
+                       a->lambda, p->bfac, exact, a->active);
   }
   PPD_HIP(hipGetLastError());
   return PPD_OK;
@@ -505,11 +803,20 @@ int launch_fold(ppd_plan* p) {
   return PPD_OK;
 }
 
+int launch_fold8(ppd_plan* p) {
+  const int nl = ((p->n_tiles + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
+  hipLaunchKernelGGL(k_fold8, dim3(nl), dim3(64 * FOLD8_SPLIT), 0, p->stream, p->gscratch, p->tile_item_off,
+                     p->tiles_x, p->tiles_y, p->Kx, p->grid_a);
+  PPD_HIP(hipGetLastError());
+  return PPD_OK;
+}
+
 int dispatch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double* part_out) {
   int slot;
   PPD_TRY(timer_begin(p, KK_DEGRID, &slot));
   int st;
   switch (p->T) {
+    case 8: st = launch_degrid<8>(p, dual, out, a, part_out); break;
     case 16: st = launch_degrid<16>(p, dual, out, a, part_out); break;
     case 32: st = launch_degrid<32>(p, dual, out, a, part_out); break;
     default: st = launch_degrid<64>(p, dual, out, a, part_out); break;
@@ -523,6 +830,7 @@ int dispatch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, 
   PPD_TRY(timer_begin(p, KK_GRID, &slot));
   int st;
   switch (p->T) {
+    case 8: st = launch_grid_mfma(p, dual, vin, a, exact); break;
     case 16: st = launch_grid<16>(p, dual, vin, a, exact); break;
     case 32: st = launch_grid<32>(p, dual, vin, a, exact); break;
     default: st = launch_grid<64>(p, dual, vin, a, exact); break;
@@ -559,6 +867,7 @@ int fold_grid(ppd_plan* p) {
   PPD_TRY(timer_begin(p, KK_FOLD, &slot));
   int st;
   switch (p->T) {
+    case 8: st = launch_fold8(p); break;
     case 16: st = launch_fold<16>(p); break;
     case 32: st = launch_fold<32>(p); break;
     default: st = launch_fold<64>(p); break;

@@ -261,9 +261,9 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
     if (D.block_off[j + 1] <= D.block_off[j])
       return fail(PPD_EINVAL, "block_off must be strictly increasing (no empty block)");
   if (!D.omega_u || !D.omega_v) return fail(PPD_EINVAL, "omega_u / omega_v required");
-  int T = D.tile == 0 ? 16 : D.tile;
-  if (T != 16 && T != 32 && T != 64) return fail(PPD_EINVAL, "tile must be 16, 32 or 64");
-  const int chunk_max = D.chunk == 0 ? 512 : D.chunk;
+  int T = D.tile == 0 ? 8 : D.tile;
+  if (T != 8 && T != 16 && T != 32 && T != 64) return fail(PPD_EINVAL, "tile must be 8, 16, 32 or 64");
+  const int chunk_max = D.chunk != 0 ? D.chunk : (T == 8 ? 128 : 512);
   if (chunk_max < 64 || chunk_max > 65536) return fail(PPD_EINVAL, "chunk must be in [64, 65536]");
   const float lim = 3.14159274f;   // float32(pi) rounds above pi
   for (int64_t i = 0; i < D.M; ++i) {
@@ -331,7 +331,10 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
       if (cnt[t + 1] > cnt[t]) tile_bins[t].push_back({b0 + cnt[t], cnt[t + 1] - cnt[t], j});
   }
   // work items: each tile's visibilities (all blocks) cut into <= chunk_max
-  // pieces of near-equal size; a piece is a list of per-block segments
+  // pieces, a piece being a list of per-block segments.  8 x 8 tiles (one
+  // wave per item, work in batches of 64) take full chunk_max pieces and a
+  // remainder, which needs the fewest batches; larger tiles (several waves
+  // per item) take pieces of near-equal size, which balances the waves.
   std::vector<Item> items;
   std::vector<Seg> segs;
   std::vector<int32_t> tile_item_off(ntiles + 1, 0);
@@ -345,7 +348,7 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
     int64_t left = total;
     while (left > 0) {
       const int64_t nit = (left + chunk_max - 1) / chunk_max;
-      int64_t want = (left + nit - 1) / nit;
+      int64_t want = p->T == 8 ? std::min<int64_t>(left, chunk_max) : (left + nit - 1) / nit;
       Item it{};
       it.tx = t % p->tiles_x;
       it.ty = t / p->tiles_x;

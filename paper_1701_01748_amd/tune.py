@@ -18,7 +18,7 @@ import numpy as np
 
 from . import ppd as P
 
-DEFAULT_CANDIDATES = ((16, 256), (16, 512), (16, 1024), (32, 512), (32, 1024), (32, 2048))
+DEFAULT_CANDIDATES = ((8, 128), (8, 256), (16, 256), (16, 512), (16, 1024), (32, 512), (32, 1024))
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ppd_mi355x_tune.json")
 
 

@@ -22,6 +22,9 @@ OP_CASES = [
     (32, 64, 2999, 2, 64, 64, False),
     (128, 128, 20000, 4, 32, 777, True),
     (16, 16, 37, 1, 32, 64, False),
+    (64, 64, 5000, 3, 8, 100, True),
+    (128, 128, 20000, 4, 8, 777, False),
+    (16, 32, 37, 1, 8, 64, True),
 ]
 
 

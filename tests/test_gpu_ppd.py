@@ -28,15 +28,16 @@ def _gpu_inputs(P, plan, pb):
     return perm, y, U
 
 
+@pytest.mark.parametrize("tile", [0, 8])
 @pytest.mark.parametrize("form", ["fused", "plain"])
 @pytest.mark.parametrize("n_itr", [1, 3])
-def test_iterations_match_oracle(form, n_itr):
+def test_iterations_match_oracle(form, n_itr, tile):
     P = require_gpu()
     import torch
-    announce(f"ppd iterate small form={form} n_itr={n_itr}")
+    announce(f"ppd iterate small form={form} n_itr={n_itr} tile={tile}")
     pb, wu, wv = _small_problem()
     n = pb.x_true.shape[0]
-    plan = P.Plan(n, n, wu, wv, pb.block_off, chunk=300)
+    plan = P.Plan(n, n, wu, wv, pb.block_off, chunk=300, tile=tile)
     perm, y, U = _gpu_inputs(P, plan, pb)
     st = P.PPDState(plan, y)
     prm = O.Params(eta=pb.eta, mu=1.0, n_itr=n_itr)
@@ -121,19 +122,20 @@ def test_workload64_snr_parity():
         assert rel_err(host(st.x), ost.x) < 1e-3
 
 
-def test_many_blocks_per_tile():
+@pytest.mark.parametrize("tile", [0, 8])
+def test_many_blocks_per_tile(tile):
     """100 blocks spread over the whole u-v plane (each tile holds points of
     every block): work items are cut at 64 segments, and both the operators
     and the iteration still match the oracle."""
     P = require_gpu()
     import torch
     from oracle import nufft as onf
-    announce("100 interleaved blocks")
+    announce(f"100 interleaved blocks tile={tile}")
     n, M, d = 32, 20000, 100
     x, wu, wv, _ = synth.small_case(n, M, seed=14, coverage="uniform")
     off = np.linspace(0, M, d + 1).astype(np.int64)
     pb = oprob.make_problem(x, wu, wv, off, synth.noise_unit(M, 214), 30.0, np.ones((n, n)), power_tol=1e-8)
-    plan = P.Plan(n, n, wu, wv, off)
+    plan = P.Plan(n, n, wu, wv, off, tile=tile)
     info = plan.info
     assert info.n_chunks > (2 * n // info.tile) ** 2          # tiles split by the segment cap
     perm, y, U = _gpu_inputs(P, plan, pb)

@@ -57,13 +57,14 @@ def _problem(seed=43, n=64, M=6000, d=3):
     return pb, wu, wv
 
 
-def test_exact_prox_iterations_match_oracle():
+@pytest.mark.parametrize("tile", [0, 8])
+def test_exact_prox_iterations_match_oracle(tile):
     P = require_gpu()
     import torch
-    announce("exact prox iterations")
+    announce(f"exact prox iterations tile={tile}")
     pb, wu, wv = _problem()
     n = pb.x_true.shape[0]
-    plan = P.Plan(n, n, wu, wv, pb.block_off)
+    plan = P.Plan(n, n, wu, wv, pb.block_off, tile=tile)
     perm = plan.permutation()
     y = dev(pb.y[perm].astype(np.complex64), torch.complex64)
     U = dev(pb.U[perm], torch.float64)

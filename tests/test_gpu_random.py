@@ -21,18 +21,19 @@ def _problem(seed=51, n=64, M=8000, d=4):
     return pb, wu, wv
 
 
-@pytest.mark.parametrize("graph,prox", [(False, "fb"), (True, "fb"), (False, "exact")])
-def test_randomised_iterations_match_oracle(graph, prox):
+@pytest.mark.parametrize("graph,prox,tile", [(False, "fb", 0), (True, "fb", 0), (False, "exact", 0),
+                                             (True, "fb", 8), (False, "exact", 8)])
+def test_randomised_iterations_match_oracle(graph, prox, tile):
     P = require_gpu()
     import torch
-    announce(f"randomised iterations graph={graph} prox={prox}")
+    announce(f"randomised iterations graph={graph} prox={prox} tile={tile}")
     pb, wu, wv = _problem()
     n, d = pb.x_true.shape[0], len(pb.eps)
     T = 8
     bm, pm = synth.active_sets(T, d, 0.5, 0.6, seed=61)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        plan = P.Plan(n, n, wu, wv, pb.block_off, stream=stream)
+        plan = P.Plan(n, n, wu, wv, pb.block_off, stream=stream, tile=tile)
         perm = plan.permutation()
         y = dev(pb.y[perm].astype(np.complex64), torch.complex64)
         U = dev(pb.U[perm], torch.float64)
