@@ -224,14 +224,18 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // Inverse rows: half rows -> image rows.  PRIMAL fuses Algorithm 3 steps
-// 28-30 and the FP64 statistics partials of the new iterate.
-template <bool PRIMAL>
+// 28-30 and the FP64 statistics partials of the new iterate; NEXT also runs
+// the forward row pass of the new x~ (the first transform of the next
+// iteration's step 4) on the rows just updated, into half_next.
+template <bool PRIMAL, bool NEXT>
 __global__ void k_fft_rows_inv(const float2* __restrict__ half, const float2* __restrict__ tw,
                                const float* __restrict__ dpx, const float* __restrict__ dpy,
                                int nx, int log2L, int rpb, float* __restrict__ x,
                                float* __restrict__ xt, const float* __restrict__ ut,
                                const float* __restrict__ x_true, double tau, double eta,
-                               double zeta, double lambda, double* __restrict__ part) {
+                               double zeta, double lambda, double* __restrict__ part,
+                               float2* __restrict__ half_next) {
+  static_assert(PRIMAL || !NEXT, "the next forward pass needs the primal update");
   extern __shared__ float2 sm[];
   __shared__ double red[16];
   const int L = 1 << log2L, Lp = padded_len(L);
@@ -254,7 +258,12 @@ __global__ void k_fft_rows_inv(const float2* __restrict__ half, const float2* __
   __syncthreads();
   lds_fft<true>(sm, log2L, rpb, Lp, tws);
   double dx2 = 0.0, xx = 0.0, ee = 0.0, tt = 0.0;
-  for (int i = tid; i < rpb * nx; i += nth) {
+  // rpb * nx <= 2 * nth (the staging capacity check on the host)
+  float xtn[FFT_PER / 2];
+#pragma unroll
+  for (int k = 0; k < FFT_PER / 2; ++k) {
+    const int i = tid + k * nth;
+    if (i >= rpb * nx) break;
     const int q = i / nx, c = i - q * nx, r = r0 + q;
     const int n = (c - (nx >> 1)) & (L - 1);
     const float val = sm[q * Lp + padi(n)].x * dpx[c] * dpy[r];
@@ -268,7 +277,9 @@ __global__ void k_fft_rows_inv(const float2* __restrict__ half, const float2* __
       const double xn = xo + lambda * (xb - xo);                              // step 29
       const float xnf = float(xn);
       x[idx] = xnf;
-      xt[idx] = float(2.0 * xb - xo);                                         // step 30
+      const float xtf = float(2.0 * xb - xo);                                 // step 30
+      xt[idx] = xtf;
+      if (NEXT) xtn[k] = xtf;
       const double dn = double(xnf) - xo;
       dx2 += dn * dn;
       xx += double(xnf) * double(xnf);
@@ -289,6 +300,27 @@ __global__ void k_fft_rows_inv(const float2* __restrict__ half, const float2* __
       part[4 * blockIdx.x + 1] = xx;
       part[4 * blockIdx.x + 2] = ee;
       part[4 * blockIdx.x + 3] = tt;
+    }
+  }
+  if (NEXT) {
+    // the same deapodisation, zero padding and wrapped placement as
+    // k_fft_rows_fwd, from the x~ values just stored
+    __syncthreads();
+    for (int i = tid; i < rpb * Lp; i += nth) sm[i] = make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < FFT_PER / 2; ++k) {
+      const int i = tid + k * nth;
+      if (i >= rpb * nx) break;
+      const int q = i / nx, c = i - q * nx, r = r0 + q;
+      const int n = (c - (nx >> 1)) & (L - 1);
+      sm[q * Lp + padi(bitrev(n, log2L))] = make_float2(xtn[k] * dpx[c] * dpy[r], 0.f);
+    }
+    __syncthreads();
+    lds_fft<false>(sm, log2L, rpb, Lp, tws);
+    for (int i = tid; i < rpb * L; i += nth) {
+      const int q = i >> log2L, k = i & (L - 1);
+      half_next[size_t(r0 + q) * L + k] = sm[q * Lp + padi(k)];
     }
   }
 }
@@ -321,23 +353,31 @@ ColCfg col_cfg(int L, int Kx) {
 
 }  // namespace
 
-int fft_forward(ppd_plan* p, const float* x) {
+int fft_rows_forward(ppd_plan* p, const float* x, float2* dst) {
   int slot;
   const RowCfg rc = row_cfg(p->Kx, p->ny);
   if (!rc.ok) return fail(PPD_EUNSUPPORTED, "fft: row launch shape exceeds the staging capacity");
   PPD_TRY(timer_begin(p, KK_FFT_ROWS_FWD, &slot));
   hipLaunchKernelGGL(k_fft_rows_fwd, dim3(rc.blocks), dim3(rc.threads), rc.lds, p->stream, x, p->dpx,
-                     p->dpy, p->twx, p->nx, p->log2Kx, rc.rpb, p->half);
+                     p->dpy, p->twx, p->nx, p->log2Kx, rc.rpb, dst);
   PPD_HIP(hipGetLastError());
-  PPD_TRY(timer_end(p, slot));
+  return timer_end(p, slot);
+}
+
+int fft_cols_forward(ppd_plan* p, const float2* src) {
+  int slot;
   const ColCfg cc = col_cfg(p->Ky, p->Kx);
   if (!cc.ok) return fail(PPD_EUNSUPPORTED, "fft: column launch shape exceeds the staging capacity");
   PPD_TRY(timer_begin(p, KK_FFT_COLS_FWD, &slot));
-  hipLaunchKernelGGL(k_fft_cols_fwd, dim3(cc.blocks), dim3(cc.threads), cc.lds, p->stream, p->half,
+  hipLaunchKernelGGL(k_fft_cols_fwd, dim3(cc.blocks), dim3(cc.threads), cc.lds, p->stream, src,
                      p->twy, p->ny, p->Kx, p->log2Ky, cc.C, cc.ngroups, p->grid_f);
   PPD_HIP(hipGetLastError());
-  PPD_TRY(timer_end(p, slot));
-  return PPD_OK;
+  return timer_end(p, slot);
+}
+
+int fft_forward(ppd_plan* p, const float* x) {
+  PPD_TRY(fft_rows_forward(p, x, p->half));
+  return fft_cols_forward(p, p->half);
 }
 
 int fft_cols_inverse(ppd_plan* p) {
@@ -358,22 +398,27 @@ int fft_adjoint(ppd_plan* p, float* x) {
   const RowCfg rc = row_cfg(p->Kx, p->ny);
   if (!rc.ok) return fail(PPD_EUNSUPPORTED, "fft: row launch shape exceeds the staging capacity");
   PPD_TRY(timer_begin(p, KK_FFT_ROWS_INV, &slot));
-  hipLaunchKernelGGL(k_fft_rows_inv<false>, dim3(rc.blocks), dim3(rc.threads), rc.lds, p->stream,
+  hipLaunchKernelGGL((k_fft_rows_inv<false, false>), dim3(rc.blocks), dim3(rc.threads), rc.lds, p->stream,
                      p->half, p->twx, p->dpx, p->dpy, p->nx, p->log2Kx, rc.rpb, x, nullptr, nullptr,
-                     nullptr, 0.0, 0.0, 0.0, 0.0, nullptr);
+                     nullptr, 0.0, 0.0, 0.0, 0.0, nullptr, nullptr);
   PPD_HIP(hipGetLastError());
   PPD_TRY(timer_end(p, slot));
   return PPD_OK;
 }
 
-int fft_rows_inverse_primal(ppd_plan* p, const PrimalArgs& a) {
+int fft_rows_inverse_primal(ppd_plan* p, const PrimalArgs& a, float2* next) {
   int slot;
   const RowCfg rc = row_cfg(p->Kx, p->ny);
   if (!rc.ok) return fail(PPD_EUNSUPPORTED, "fft: row launch shape exceeds the staging capacity");
   PPD_TRY(timer_begin(p, KK_FFT_ROWS_INV, &slot));
-  hipLaunchKernelGGL(k_fft_rows_inv<true>, dim3(rc.blocks), dim3(rc.threads), rc.lds, p->stream,
-                     p->half, p->twx, p->dpx, p->dpy, p->nx, p->log2Kx, rc.rpb, a.x, a.xt, a.ut,
-                     a.x_true, a.tau, a.eta, a.zeta, a.lambda, a.part);
+  if (next)
+    hipLaunchKernelGGL((k_fft_rows_inv<true, true>), dim3(rc.blocks), dim3(rc.threads), rc.lds, p->stream,
+                       p->half, p->twx, p->dpx, p->dpy, p->nx, p->log2Kx, rc.rpb, a.x, a.xt, a.ut,
+                       a.x_true, a.tau, a.eta, a.zeta, a.lambda, a.part, next);
+  else
+    hipLaunchKernelGGL((k_fft_rows_inv<true, false>), dim3(rc.blocks), dim3(rc.threads), rc.lds, p->stream,
+                       p->half, p->twx, p->dpx, p->dpy, p->nx, p->log2Kx, rc.rpb, a.x, a.xt, a.ut,
+                       a.x_true, a.tau, a.eta, a.zeta, a.lambda, a.part, nullptr);
   PPD_HIP(hipGetLastError());
   PPD_TRY(timer_end(p, slot));
   return PPD_OK;

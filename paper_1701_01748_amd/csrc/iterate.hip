@@ -147,7 +147,7 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
   PPD_HIP(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
   {
     OnStream on(p, p->aux);
-    PPD_TRY(fft_forward(p, xt));                              // step 4: a = F Z x~
+    PPD_TRY(fft_cols_forward(p, p->half_f));                  // step 4: a = F Z x~ (rows done)
     if (c.form == PPD_FORM_FUSED && c.prox == PPD_PROX_EXACT) {
       PPD_TRY(degrid_dual(p, c.dual, p->part));               // step 10 argument w
       PPD_TRY(secular_solve(p, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.n_newton));  // prox^U_h(w)
@@ -173,7 +173,8 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
   PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda, c.W, c.basis_active));   // steps 19-20
   PPD_TRY(sara_synthesis(p, c.u, p->ut, c.W));              // step 21, summed over i
   PPD_HIP(hipStreamWaitEvent(p->stream, p->ev_join, 0));
-  return fft_rows_inverse_primal(p, c.primal);              // steps 28-30
+  // steps 28-30, and the forward row pass of the new x~ for the next step 4
+  return fft_rows_inverse_primal(p, c.primal, p->half_f);
 }
 
 std::string graph_key(const IterCtx& c) {
@@ -257,6 +258,9 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   c.n_newton = prm->n_newton == 0 ? 12 : prm->n_newton;
 
   if (n_iter > 0) {
+    // the first iteration's forward row pass; each iteration then leaves
+    // the next one's
+    PPD_TRY(fft_rows_forward(p, st->xt, p->half_f));
     if (prm->use_graph) {
       const std::string key = graph_key(c);
       if (!p->graph_exec || key != p->graph_key) {

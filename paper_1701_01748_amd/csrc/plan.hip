@@ -450,6 +450,7 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   A(dalloc(p, &p->grid_f, K2));
   A(dalloc(p, &p->grid_a, K2));
   A(dalloc(p, &p->half, size_t(p->ny) * p->Kx));
+  A(dalloc(p, &p->half_f, size_t(p->ny) * p->Kx));
   A(dalloc(p, &p->ybuf, M));
   A(dalloc(p, &p->wbuf, M));
   A(dalloc(p, &p->gabuf, M));

@@ -109,6 +109,7 @@ struct ppd_plan {
   float2* grid_f = nullptr;                // forward spectrum  Ky x Kx
   float2* grid_a = nullptr;                // adjoint accumulation Ky x Kx
   float2* half = nullptr;                  // ny x Kx intermediate
+  float2* half_f = nullptr;                // ny x Kx forward row pass of x~ (iterations)
   float2* ybuf = nullptr;                  // [M] complex64 scratch
   double2* wbuf = nullptr;                 // [M] complex128 w (plain form)
   float2* gabuf = nullptr;                 // [M] complex64 Theta G a (fused form; w is rebuilt from it)
@@ -153,7 +154,9 @@ int timer_begin(ppd_plan* p, int kind, int* slot);
 int timer_end(ppd_plan* p, int slot);
 
 // ---- component launchers (each returns a PPD_* status) -------------------
-int fft_forward(ppd_plan* p, const float* x);                  // x -> grid_f
+int fft_forward(ppd_plan* p, const float* x);                  // x -> grid_f (via half)
+int fft_rows_forward(ppd_plan* p, const float* x, float2* dst);  // x -> dst (ny x Kx)
+int fft_cols_forward(ppd_plan* p, const float2* src);           // src (ny x Kx) -> grid_f
 int fft_adjoint(ppd_plan* p, float* x);                        // grid_a -> x (plain)
 int fft_cols_inverse(ppd_plan* p);                             // grid_a -> half
 struct PrimalArgs {
@@ -161,7 +164,9 @@ struct PrimalArgs {
   double tau, eta, zeta, lambda;
   double* part;                                                // [ny][4]
 };
-int fft_rows_inverse_primal(ppd_plan* p, const PrimalArgs& a);  // half -> primal update
+// half -> primal update; with next != NULL also the forward row pass of the
+// new x~ into next (ny x Kx)
+int fft_rows_inverse_primal(ppd_plan* p, const PrimalArgs& a, float2* next);
 int fold_grid(ppd_plan* p);                                    // gscratch -> grid_a
 
 int degrid_plain(ppd_plan* p, float2* out);                    // grid_f -> out (plan order)
