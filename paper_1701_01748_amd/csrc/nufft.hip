@@ -47,6 +47,17 @@ __device__ __forceinline__ void taps_for(float omu, float omv, double su, double
   kb_weights(float(tv - fv), coef, t.wy);
 }
 
+// The coefficients kb_weights reads (taps 0..3), loaded with uniform
+// addresses so that they stay in scalar registers (an LDS copy would be
+// re-read by every lane for every batch).
+struct KbCoef {
+  float c[KB_TAPS / 2 * KB_NC];
+};
+__device__ __forceinline__ void load_kb(const float* __restrict__ kbc, KbCoef& k) {
+#pragma unroll
+  for (int i = 0; i < KB_TAPS / 2 * KB_NC; ++i) k.c[i] = kbc[i];
+}
+
 #ifndef PPD_DEGRID_WAVES
 #define PPD_DEGRID_WAVES 4
 #endif
@@ -77,7 +88,6 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
   constexpr int R = T + 7;
   constexpr int NW = DegridCfg<T>::NW;
   __shared__ float2 reg[R * R];
-  __shared__ float coef[KB_TAPS * KB_NC];
   __shared__ ItemTab tab;
   __shared__ double s_q[NW][MAX_ITEM_SEGS], s_r[NW][MAX_ITEM_SEGS];
   const int ii = xcd_remap(blockIdx.x, gridDim.x);
@@ -98,7 +108,8 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
     }
   }
   load_item_tab(it, segs, tab);
-  for (int i = threadIdx.x; i < KB_TAPS * KB_NC; i += blockDim.x) coef[i] = kbc[i];
+  KbCoef kbw;
+  load_kb(kbc, kbw);
   if (DUAL)
     for (int i = threadIdx.x; i < NW * MAX_ITEM_SEGS; i += blockDim.x) {
       (&s_q[0][0])[i] = 0.0;
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
       const double Ue = DUAL ? cb.U : 1.0;
       const double2 ze = cb.z;
       Taps t;
-      taps_for<T>(omu, omv, su, sv, Kx, Ky, c0, r0, coef, t);
+      taps_for<T>(omu, omv, su, sv, Kx, Ky, c0, r0, kbw.c, t);
       float ax = 0.f, ay = 0.f;
 #pragma unroll 2
       for (int a = 0; a < KB_TAPS; ++a) {
@@ -329,7 +340,6 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
   constexpr int WXS = KB_TAPS + 1;             // staging stride per visibility (bank spread)
   __shared__ float2 wxv[NW][64 * WXS];         // wx[b] * value, per visibility of the batch
   __shared__ float wyb[NW][64 * WXS];          // wy[a]
-  __shared__ float coef[KB_TAPS * KB_NC];
   __shared__ ItemTab tab;
   const int ii = xcd_remap(blockIdx.x, gridDim.x);
   if (ii >= n_items) return;
@@ -339,7 +349,8 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
   const int uwid = __builtin_amdgcn_readfirstlane(wid);   // wave-uniform
   load_item_tab(it, segs, tab);
   for (int i = threadIdx.x; i < NW * C * R * RS; i += blockDim.x) (&acc[0][0][0])[i] = make_float2(0.f, 0.f);
-  for (int i = threadIdx.x; i < KB_TAPS * KB_NC; i += blockDim.x) coef[i] = kbc[i];
+  KbCoef kbw;
+  load_kb(kbc, kbw);
   __syncthreads();
   float2 (*myacc)[R * RS] = acc[wid];
   float2* mywxv = wxv[wid];
@@ -369,7 +380,7 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     float vx = 0.f, vy = 0.f;
     Taps t;
     if (lane < nb) {
-      taps_for<T>(bt.ou, bt.ov, su, sv, Kx, Ky, c0, r0, coef, t);
+      taps_for<T>(bt.ou, bt.ov, su, sv, Kx, Ky, c0, r0, kbw.c, t);
       const float2 val = grid_value<DUAL>(bt, mu, lambda, exact, znew, vnew);
       vx = val.x * bt.th;
       vy = val.y * bt.th;
@@ -444,8 +455,9 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
 // v_mfma_f32_16x16x4_f32 (real and imaginary parts), in FP32 registers.  A
 // batch of 64 visibilities is prepared one per lane, as in k_grid, and
 // written to LDS as zero-padded 16-entry weight rows (the A operand) and
-// value-scaled weight rows (B); lane l of a product step then reads row
-// 4 g + l / 16, entry l mod 16, of each.  No read-modify-write of LDS.
+// value-scaled weight rows (B), 32 rows at a time; lane l of a product step
+// then reads row 4 g + l / 16, entry l mod 16, of each.  No read-modify-write
+// of LDS.
 //
 // An 8 x 8 tile holds about one batch, so a single-wave workgroup takes a
 // run of consecutive items, and the wave's (item, batch) steps form one
@@ -496,11 +508,11 @@ __global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
     double lambda, const double2* __restrict__ bfac, int exact, const uint8_t* __restrict__ active) {
   constexpr int T = GM_T, R = T + 7, WPG = PPD_GRIDM_WPG;
   static_assert(R <= 16, "the region must fit one 16 x 16 product tile");
-  __shared__ float sAw[WPG][64 * GM_AS];
-  __shared__ float2 sBw[WPG][64 * GM_BS];
-  __shared__ float coef[KB_TAPS * KB_NC];
+  __shared__ float sAw[WPG][32 * GM_AS];
+  __shared__ float2 sBw[WPG][32 * GM_BS];
   __shared__ ItemTab tabsw[WPG][2];   // per wave: current and next item
-  for (int i = threadIdx.x; i < KB_TAPS * KB_NC; i += blockDim.x) coef[i] = kbc[i];
+  KbCoef kbw;
+  load_kb(kbc, kbw);
   __syncthreads();
   // each wave of the workgroup works alone from here on
   const int wid = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
@@ -527,8 +539,8 @@ __global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
   int total = __builtin_amdgcn_readfirstlane(tabs[0].pre[field(itl.seg1, i0) - field(itl.seg0, i0)]);
   GridBatch bn{};
   grid_load<DUAL>(src, tabs[0], total, lane, 0, sb, bn);
-  float* arow = sA + lane * GM_AS;
-  float2* brow = sB + lane * GM_BS;
+  float* arow = sA + (lane & 31) * GM_AS;
+  float2* brow = sB + (lane & 31) * GM_BS;
   while (true) {
     const GridBatch bt = bn;
     const int nb = min(64, total - kb * 64);
@@ -553,7 +565,7 @@ __global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
     float vx = 0.f, vy = 0.f;
     Taps t;
     if (lane < nb) {
-      taps_for<T>(bt.ou, bt.ov, su, sv, Kx, Ky, c0, r0, coef, t);
+      taps_for<T>(bt.ou, bt.ov, su, sv, Kx, Ky, c0, r0, kbw.c, t);
       const float2 val = grid_value<DUAL>(bt, mu, lambda, exact, znew, vnew);
       vx = val.x * bt.th;
       vy = val.y * bt.th;
@@ -567,35 +579,42 @@ __global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
         t.wy[m] = 0.f;
       }
     }
-    // the 8 taps at the footprint offset and zeros in the 8 other entries
+    // The batch goes through LDS in two halves of 32 rows (half the staging
+    // memory: more waves per CU): lanes 0-31 write their rows and the first
+    // 8 product steps read them, then lanes 32-63.  Each lane writes the 8
+    // taps at the footprint offset and zeros in the 8 other entries.
+    for (int h = 0; h * 32 < nb; ++h) {
+      if ((lane >> 5) == h) {
 #pragma unroll
-    for (int m = 0; m < KB_TAPS; ++m) {
-      arow[t.ov + m] = t.wy[m];
-      arow[(t.ov + KB_TAPS + m) & 15] = 0.f;
-      brow[t.ou + m] = make_float2(t.wx[m] * vx, t.wx[m] * vy);
-      brow[(t.ou + KB_TAPS + m) & 15] = make_float2(0.f, 0.f);
+        for (int m = 0; m < KB_TAPS; ++m) {
+          arow[t.ov + m] = t.wy[m];
+          arow[(t.ov + KB_TAPS + m) & 15] = 0.f;
+          brow[t.ou + m] = make_float2(t.wx[m] * vx, t.wx[m] * vy);
+          brow[(t.ou + KB_TAPS + m) & 15] = make_float2(0.f, 0.f);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      // two accumulator pairs (even / odd product steps): independent chains
+      const int ng = (min(32, nb - 32 * h) + 3) >> 2;
+      int g = 0;
+      for (; g + 2 <= ng; g += 2) {
+        const int ra = 4 * g + gq, rb = ra + 4;
+        const float a0 = sA[ra * GM_AS + gc], a1 = sA[rb * GM_AS + gc];
+        const float2 b0 = sB[ra * GM_BS + gc], b1 = sB[rb * GM_BS + gc];
+        accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.x, accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.y, acci, 0, 0, 0);
+        accr2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1.x, accr2, 0, 0, 0);
+        acci2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1.y, acci2, 0, 0, 0);
+      }
+      if (g < ng) {
+        const int ra = 4 * g + gq;
+        const float a0 = sA[ra * GM_AS + gc];
+        const float2 b0 = sB[ra * GM_BS + gc];
+        accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.x, accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.y, acci, 0, 0, 0);
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
-    // two accumulator pairs (even / odd product steps): independent chains
-    const int ng = (nb + 3) >> 2;
-    int g = 0;
-    for (; g + 2 <= ng; g += 2) {
-      const int ra = 4 * g + gq, rb = ra + 4;
-      const float a0 = sA[ra * GM_AS + gc], a1 = sA[rb * GM_AS + gc];
-      const float2 b0 = sB[ra * GM_BS + gc], b1 = sB[rb * GM_BS + gc];
-      accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.x, accr, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.y, acci, 0, 0, 0);
-      accr2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1.x, accr2, 0, 0, 0);
-      acci2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1.y, acci2, 0, 0, 0);
-    }
-    if (g < ng) {
-      const int ra = 4 * g + gq;
-      const float a0 = sA[ra * GM_AS + gc];
-      const float2 b0 = sB[ra * GM_BS + gc];
-      accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.x, accr, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.y, acci, 0, 0, 0);
-    }
-    __builtin_amdgcn_wave_barrier();
     if (DUAL && lane < nb && bt.act) {
       z[bt.pi] = znew;
       v[bt.pi] = vnew;
