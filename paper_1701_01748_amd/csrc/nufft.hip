@@ -169,7 +169,7 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
       Taps t;
       taps_for<T>(omu, omv, su, sv, Kx, Ky, c0, r0, kbw.c, t);
       float ax = 0.f, ay = 0.f;
-#pragma unroll 2
+#pragma unroll
       for (int a = 0; a < KB_TAPS; ++a) {
         const float2* row = reg + (t.ov + a) * R + t.ou;
         float sx = 0.f, sy = 0.f;
@@ -688,7 +688,8 @@ __global__ __launch_bounds__(FOLD_CELLS) void k_fold(const float2* __restrict__ 
 // 8 x 8 tiles: one tile per workgroup, FOLD8_SPLIT threads per cell, thread
 // p taking every FOLD8_SPLIT-th slot from p (a tile's region may come from
 // dozens of items, and their loads are independent); the parts are added in
-// a fixed order.
+// a fixed order.  Workgroups take the tiles in the plan's fold order (most
+// item regions first), so the longest sums start first.
 #ifndef PPD_FOLD8_SPLIT
 #define PPD_FOLD8_SPLIT 2
 #endif
@@ -714,12 +715,13 @@ __device__ __forceinline__ void fold_items_strided(const float2* __restrict__ sc
 }
 
 __global__ __launch_bounds__(64 * FOLD8_SPLIT) void k_fold8(const float2* __restrict__ scratch,
-                                                            const int32_t* __restrict__ tio, int tiles_x,
+                                                            const int32_t* __restrict__ tio,
+                                                            const int32_t* __restrict__ order, int tiles_x,
                                                             int tiles_y, int Kx, float2* __restrict__ grid) {
   constexpr int T = 8, R = T + 7;
   __shared__ float2 part[FOLD8_SPLIT][64];
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  if (t >= tiles_x * tiles_y) return;   // uniform over the workgroup
+  if (int(blockIdx.x) >= tiles_x * tiles_y) return;   // uniform over the workgroup
+  const int t = order[blockIdx.x];
   const int p = threadIdx.x >> 6, c = threadIdx.x & 63;
   const int tx = t % tiles_x, ty = t / tiles_x;
   const int lx = (tx + tiles_x - 1) % tiles_x, uy = (ty + tiles_y - 1) % tiles_y;
@@ -823,9 +825,8 @@ int launch_fold(ppd_plan* p) {
 }
 
 int launch_fold8(ppd_plan* p) {
-  const int nl = ((p->n_tiles + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
-  hipLaunchKernelGGL(k_fold8, dim3(nl), dim3(64 * FOLD8_SPLIT), 0, p->stream, p->gscratch, p->tile_item_off,
-                     p->tiles_x, p->tiles_y, p->Kx, p->grid_a);
+  hipLaunchKernelGGL(k_fold8, dim3(p->n_tiles), dim3(64 * FOLD8_SPLIT), 0, p->stream, p->gscratch,
+                     p->tile_item_off, p->fold_order, p->tiles_x, p->tiles_y, p->Kx, p->grid_a);
   PPD_HIP(hipGetLastError());
   return PPD_OK;
 }

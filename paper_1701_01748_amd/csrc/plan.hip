@@ -370,6 +370,21 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
     }
   }
   tile_item_off[ntiles] = int32_t(items.size());
+  // fold order: tiles by decreasing number of item regions to sum (own and
+  // the left / upper / upper-left halos), so that the long sums start first
+  std::vector<int32_t> fold_order(ntiles);
+  {
+    std::vector<int32_t> work(ntiles);
+    for (int t = 0; t < ntiles; ++t) {
+      const int tx = t % p->tiles_x, ty = t / p->tiles_x;
+      const int lx = (tx + p->tiles_x - 1) % p->tiles_x, uy = (ty + p->tiles_y - 1) % p->tiles_y;
+      auto n = [&](int u) { return tile_item_off[u + 1] - tile_item_off[u]; };
+      work[t] = n(t) + n(ty * p->tiles_x + lx) + n(uy * p->tiles_x + tx) + n(uy * p->tiles_x + lx);
+    }
+    for (int t = 0; t < ntiles; ++t) fold_order[t] = t;
+    std::stable_sort(fold_order.begin(), fold_order.end(),
+                     [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+  }
   p->n_items = int(items.size());
   p->n_segs = int(segs.size());
   p->n_tiles = ntiles;
@@ -436,6 +451,7 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   A(dalloc(p, &p->items, p->n_items));
   A(dalloc(p, &p->segs, p->n_segs));
   A(dalloc(p, &p->tile_item_off, ntiles + 1));
+  A(dalloc(p, &p->fold_order, ntiles));
   A(dalloc(p, &p->bseg_ids, p->n_segs));
   A(dalloc(p, &p->bseg_off_d, p->d + 1));
   A(dalloc(p, &p->bfac, p->d));
@@ -489,6 +505,7 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   up(p->items, items.data(), sizeof(Item) * p->n_items);
   up(p->segs, segs.data(), sizeof(Seg) * p->n_segs);
   up(p->tile_item_off, tile_item_off.data(), 4 * (ntiles + 1));
+  up(p->fold_order, fold_order.data(), 4 * ntiles);
   up(p->bseg_ids, bids.data(), 4 * p->n_segs);
   up(p->bseg_off_d, p->bseg_off.data(), 4 * (p->d + 1));
   up(p->vis_block, vblk.data(), 4 * M);
