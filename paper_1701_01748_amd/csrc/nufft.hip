@@ -688,8 +688,9 @@ __global__ __launch_bounds__(FOLD_CELLS) void k_fold(const float2* __restrict__ 
 // 8 x 8 tiles: one tile per workgroup, FOLD8_SPLIT threads per cell, thread
 // p taking every FOLD8_SPLIT-th slot from p (a tile's region may come from
 // dozens of items, and their loads are independent); the parts are added in
-// a fixed order.  Workgroups take the tiles in the plan's fold order (most
-// item regions first), so the longest sums start first.
+// a fixed order.  Workgroups take the tiles in the plan's fold order: tile
+// rows spread over the XCDs, and on each XCD the tiles with the most item
+// regions first, so the longest sums start first.
 #ifndef PPD_FOLD8_SPLIT
 #define PPD_FOLD8_SPLIT 2
 #endif
@@ -720,8 +721,8 @@ __global__ __launch_bounds__(64 * FOLD8_SPLIT) void k_fold8(const float2* __rest
                                                             int tiles_y, int Kx, float2* __restrict__ grid) {
   constexpr int T = 8, R = T + 7;
   __shared__ float2 part[FOLD8_SPLIT][64];
-  if (int(blockIdx.x) >= tiles_x * tiles_y) return;   // uniform over the workgroup
-  const int t = order[blockIdx.x];
+  const int t = order[xcd_remap(blockIdx.x, gridDim.x)];
+  if (t < 0) return;   // padding; uniform over the workgroup
   const int p = threadIdx.x >> 6, c = threadIdx.x & 63;
   const int tx = t % tiles_x, ty = t / tiles_x;
   const int lx = (tx + tiles_x - 1) % tiles_x, uy = (ty + tiles_y - 1) % tiles_y;
@@ -825,7 +826,7 @@ int launch_fold(ppd_plan* p) {
 }
 
 int launch_fold8(ppd_plan* p) {
-  hipLaunchKernelGGL(k_fold8, dim3(p->n_tiles), dim3(64 * FOLD8_SPLIT), 0, p->stream, p->gscratch,
+  hipLaunchKernelGGL(k_fold8, dim3(p->n_fold_launch), dim3(64 * FOLD8_SPLIT), 0, p->stream, p->gscratch,
                      p->tile_item_off, p->fold_order, p->tiles_x, p->tiles_y, p->Kx, p->grid_a);
   PPD_HIP(hipGetLastError());
   return PPD_OK;

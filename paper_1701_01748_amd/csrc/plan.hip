@@ -370,9 +370,13 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
     }
   }
   tile_item_off[ntiles] = int32_t(items.size());
-  // fold order: tiles by decreasing number of item regions to sum (own and
-  // the left / upper / upper-left halos), so that the long sums start first
-  std::vector<int32_t> fold_order(ntiles);
+  // fold order: the tiles of tile row ty go to XCD ty mod 8 (horizontal
+  // neighbours, which share cache lines of the item regions, meet in one L2;
+  // the dense rows are spread over all XCDs), and each XCD takes its tiles
+  // by decreasing number of item regions to sum (own and left / upper /
+  // upper-left halos), so the long sums start first.  Lists are padded to a
+  // common length with -1 (no tile).
+  std::vector<int32_t> fold_order;
   {
     std::vector<int32_t> work(ntiles);
     for (int t = 0; t < ntiles; ++t) {
@@ -381,9 +385,17 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
       auto n = [&](int u) { return tile_item_off[u + 1] - tile_item_off[u]; };
       work[t] = n(t) + n(ty * p->tiles_x + lx) + n(uy * p->tiles_x + tx) + n(uy * p->tiles_x + lx);
     }
-    for (int t = 0; t < ntiles; ++t) fold_order[t] = t;
-    std::stable_sort(fold_order.begin(), fold_order.end(),
-                     [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+    std::vector<std::vector<int32_t>> lists(MAX_XCD);
+    for (int t = 0; t < ntiles; ++t) lists[(t / p->tiles_x) % MAX_XCD].push_back(t);
+    size_t per = 0;
+    for (auto& l : lists) {
+      std::stable_sort(l.begin(), l.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+      per = std::max(per, l.size());
+    }
+    for (auto& l : lists) {
+      l.resize(per, -1);
+      fold_order.insert(fold_order.end(), l.begin(), l.end());
+    }
   }
   p->n_items = int(items.size());
   p->n_segs = int(segs.size());
@@ -451,7 +463,8 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   A(dalloc(p, &p->items, p->n_items));
   A(dalloc(p, &p->segs, p->n_segs));
   A(dalloc(p, &p->tile_item_off, ntiles + 1));
-  A(dalloc(p, &p->fold_order, ntiles));
+  A(dalloc(p, &p->fold_order, fold_order.size()));
+  p->n_fold_launch = int(fold_order.size());
   A(dalloc(p, &p->bseg_ids, p->n_segs));
   A(dalloc(p, &p->bseg_off_d, p->d + 1));
   A(dalloc(p, &p->bfac, p->d));
@@ -505,7 +518,7 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   up(p->items, items.data(), sizeof(Item) * p->n_items);
   up(p->segs, segs.data(), sizeof(Seg) * p->n_segs);
   up(p->tile_item_off, tile_item_off.data(), 4 * (ntiles + 1));
-  up(p->fold_order, fold_order.data(), 4 * ntiles);
+  up(p->fold_order, fold_order.data(), 4 * fold_order.size());
   up(p->bseg_ids, bids.data(), 4 * p->n_segs);
   up(p->bseg_off_d, p->bseg_off.data(), 4 * (p->d + 1));
   up(p->vis_block, vblk.data(), 4 * M);

@@ -94,7 +94,8 @@ struct ppd_plan {
   ppd::Item* items = nullptr;
   ppd::Seg* segs = nullptr;
   int32_t* tile_item_off = nullptr;        // [n_tiles+1] items of each tile
-  int32_t* fold_order = nullptr;           // [n_tiles] tiles by decreasing fold work
+  int32_t* fold_order = nullptr;           // [n_fold_launch] tile per fold workgroup (-1: none)
+  int n_fold_launch = 0;                   // multiple of MAX_XCD
   int32_t* bseg_ids = nullptr;             // segment ids grouped by block
   int32_t* bseg_off_d = nullptr;           // [d+1]
   float2* gscratch = nullptr;              // [n_items][(T+7)^2] gridding partials
