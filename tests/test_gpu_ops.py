@@ -183,3 +183,34 @@ def test_operator_norm_matches_oracle():
     Ud = dev(U[plan.permutation()], torch.float64)
     g, it = P.ppd_op_norm(plan, Ud, dev(inp.power_start.astype(np.float32), torch.float32), 2000, 1e-10)
     assert abs(g - ref) / ref < 1e-5, (g, ref, it)
+
+
+@pytest.mark.parametrize("M", [1, 63, 64, 65, 127, 128, 129, 300])
+def test_tile8_item_boundaries(M):
+    """All points in one 8 x 8 tile whose halo wraps around the grid edge
+    (first taps in the last tile row and column), so that one tile's item
+    split (128-point pieces plus a remainder), the batch tails (64-point
+    batches), the run pipeline of the matrix-core gridding and the fold's
+    wrapped halos are exercised at their boundaries; two blocks share the
+    tile when M > 1."""
+    P = require_gpu()
+    import torch
+    announce(f"tile-8 boundaries M={M}")
+    n = 32
+    K = 2 * n
+    rng = np.random.default_rng(M)
+    # first-tap cell floor(omega K / 2 pi) - 3 in [K - 8, K): floor in [-5, 3)
+    wu = (rng.uniform(-4.95, 2.95, M) * 2 * np.pi / K).astype(np.float32)
+    wv = (rng.uniform(-4.95, 2.95, M) * 2 * np.pi / K).astype(np.float32)
+    off = np.array([0, M], np.int64) if M == 1 else np.array([0, M // 2, M], np.int64)
+    plan = P.Plan(n, n, wu, wv, off, tile=8)
+    info = plan.info
+    assert info.tile == 8 and info.n_chunks == -(-M // 128)
+    op = onf.Nufft(wu, wv, n, n)
+    x = rng.standard_normal((n, n)).astype(np.float32)
+    perm = plan.permutation()
+    y = host(P.ppd_phi(plan, dev(x, torch.float32)))
+    assert_op_close(y, op.phi(x.astype(np.float64))[perm], what="phi")
+    v = (rng.standard_normal(M) + 1j * rng.standard_normal(M)).astype(np.complex64)
+    xg = host(P.ppd_phit(plan, dev(v, torch.complex64), order=P.ORDER_USER))
+    assert_op_close(xg, op.phit(v.astype(np.complex128)), what="phit")
