@@ -6,7 +6,8 @@ radial coverage in 16 uneven blocks (20k..200k), 30 dB input SNR, SARA with
 3 levels, one Algorithm 2 sub-iteration.  A step is one full iteration of
 Algorithm 3 (forward FFT, degridding with the fused dual update, gridding,
 inverse FFT, SARA analysis + dual clip + synthesis, primal update), replayed
-from a captured HIP graph, inputs resident in HBM.
+from a captured HIP graph or launched eagerly on two streams (both timed,
+the faster is the value), inputs resident in HBM.
 
 Prints one JSON line: PPD iterations/s (value), Phi / Phi^H visibilities/s,
 the plain (unfused, per-block FP64) form for comparison, the roofline of the
@@ -165,20 +166,25 @@ def main():
     kw = dict(eta=eta, tau=0.49, zeta=1.0, lam=1.0, alpha=1e-4, mu=1.0, n_itr=args.n_itr)
     state = P.PPDState(plan, y)
 
-    # ---- timed region: graph replay of the fused iteration ---------------------
-    P.ppd_iterate(plan, state, y, U, eps, args.warmup, use_graph=True, stats=False, **kw)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    P.ppd_iterate(plan, state, y, U, eps, args.steps, use_graph=True, stats=False, **kw)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall_s = t1 - t0
-    ev_ms = e0.elapsed_time(e1)
+    # ---- timed region: the fused iteration, replayed from a HIP graph and
+    # launched eagerly (two streams); the faster of the two is the value ----
+    def timed(graph: bool):
+        P.ppd_iterate(plan, state, y, U, eps, args.warmup, use_graph=graph, stats=False, **kw)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        P.ppd_iterate(plan, state, y, U, eps, args.steps, use_graph=graph, stats=False, **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e0.elapsed_time(e1)
+
+    wall_g, ev_g = timed(True)
+    wall_e, ev_e = timed(False)
+    use_graph = wall_g <= wall_e
+    wall_s, ev_ms = (wall_g, ev_g) if use_graph else (wall_e, ev_e)
     value = args.steps / wall_s
-    st = P.ppd_iterate(plan, state, y, U, eps, 1, use_graph=True, x_true=x_true, **kw)
+    st = P.ppd_iterate(plan, state, y, U, eps, 1, use_graph=use_graph, x_true=x_true, **kw)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "PPD iterations/s", "n_gpus": 1,
@@ -186,9 +192,11 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "image": f"{n}x{n}", "M": M, "blocks": int(len(off) - 1),
-                   "n_itr": args.n_itr, "levels": 3, "form": "fused, hip graph", "tile": info.tile,
+                   "n_itr": args.n_itr, "levels": 3,
+                   "form": "fused, hip graph" if use_graph else "fused, eager two-stream", "tile": info.tile,
                    "chunk": info.chunk},
         "event_ms_per_step": round(ev_ms / args.steps, 4),
+        "graph_iters_per_s": round(args.steps / wall_g, 2), "eager_iters_per_s": round(args.steps / wall_e, 2),
         "snr_db_after": round(st["snr_db"], 3), "iterations_done": st["iter"],
         "residual_max_over_eps": round(st["residual_max"], 4),
         "op_norm_power_iters": it_pow,
@@ -256,7 +264,6 @@ def main():
             torch.cuda.synchronize()
             return T / (time.perf_counter() - ta)
 
-        out["fused_eager_iters_per_s"] = round(iters_per_s(P.FORM_FUSED, False, 50), 2)
         out["plain_iters_per_s"] = round(iters_per_s(P.FORM_PLAIN, False, 20), 2)
 
     if not args.no_cpu_baseline:

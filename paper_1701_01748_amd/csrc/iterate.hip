@@ -123,6 +123,7 @@ struct IterCtx {
   int form;
   int prox, n_newton;
   const uint8_t* basis_active;
+  bool sara_forked;   // SARA on the second stream (eager), else the data path (graph)
 };
 
 // Runs the plan's launches on another stream for the lifetime of the object.
@@ -133,45 +134,64 @@ struct OnStream {
   ~OnStream() { p->stream = saved; }
 };
 
-// One iteration of Algorithm 3 on the plan's stream.  Steps 19-21 (SARA
-// dual update and synthesis) need only x~ and u, so the data-fidelity path
-// (steps 4-12 and the inverse FFT of step 28) is forked to the plan's second
-// stream and runs concurrently with them; the primal update (steps 28-30)
-// waits for both on the plan's stream.  Under graph capture the fork and
-// join become graph edges.  (Forking SARA instead and keeping the data path
-// on the plan's stream measured ~10 us slower per replayed iteration: the
-// join then moved the critical path across hardware queues twice.)
+// The data-fidelity path of one iteration (steps 4-12 and the inverse
+// column FFT of step 28) on the plan's current stream.
+int data_path(ppd_plan* p, const IterCtx& c) {
+  PPD_TRY(fft_cols_forward(p, p->half_f));                  // step 4: a = F Z x~ (rows done)
+  if (c.form == PPD_FORM_FUSED && c.prox == PPD_PROX_EXACT) {
+    PPD_TRY(degrid_dual(p, c.dual, p->part));               // step 10 argument w
+    PPD_TRY(secular_solve(p, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.n_newton));  // prox^U_h(w)
+    PPD_TRY(grid_dual_exact(p, c.dual));                    // steps 10-12
+  } else if (c.form == PPD_FORM_FUSED) {
+    double* pa = p->part;
+    double* pb = p->part + p->n_segs;
+    PPD_TRY(degrid_dual(p, c.dual, pa));                    // step 10 argument, first Alg. 2 step
+    for (int s = 1; s < c.dual.n_itr; ++s) {
+      PPD_TRY(alg2_launch(p, 1, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb,
+                          c.dual.active));
+      std::swap(pa, pb);
+    }
+    PPD_TRY(grid_dual(p, c.dual, pa));                      // steps 10-12
+  } else {
+    PPD_TRY(degrid_plain(p, p->ybuf));
+    PPD_TRY(plain_dual(p, c.dual));                         // steps 10-11, block by block
+    PPD_TRY(grid_plain(p, c.dual.v));                       // step 12
+  }
+  return fft_cols_inverse(p);
+}
+
+// Steps 19-21 (SARA dual update and synthesis) on the plan's current stream.
+int sara_path(ppd_plan* p, const IterCtx& c) {
+  PPD_TRY(sara_dual(p, c.primal.xt, c.u, c.alpha, c.lambda, c.W, c.basis_active));   // steps 19-20
+  return sara_synthesis(p, c.u, p->ut, c.W);                // step 21, summed over i
+}
+
+// One iteration of Algorithm 3 on the plan's stream.  SARA needs only x~
+// and u, so it runs concurrently with the data-fidelity path, one of the two
+// forked to the plan's second stream; the primal update (steps 28-30) waits
+// for both on the plan's stream.  Eager, SARA is forked and the data path
+// stays on the plan's stream (no queue hand-off at its start); captured
+// into a graph, the data path is forked: replayed graphs put a forked SARA
+// branch's join, and with it the primal update, on the other hardware queue
+// (measured 163 against 155 us per iteration).
 int one_iteration(ppd_plan* p, const IterCtx& c) {
-  const float* xt = c.primal.xt;
   PPD_HIP(hipEventRecord(p->ev_fork, p->stream));
   PPD_HIP(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
-  {
-    OnStream on(p, p->aux);
-    PPD_TRY(fft_cols_forward(p, p->half_f));                  // step 4: a = F Z x~ (rows done)
-    if (c.form == PPD_FORM_FUSED && c.prox == PPD_PROX_EXACT) {
-      PPD_TRY(degrid_dual(p, c.dual, p->part));               // step 10 argument w
-      PPD_TRY(secular_solve(p, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.n_newton));  // prox^U_h(w)
-      PPD_TRY(grid_dual_exact(p, c.dual));                    // steps 10-12
-    } else if (c.form == PPD_FORM_FUSED) {
-      double* pa = p->part;
-      double* pb = p->part + p->n_segs;
-      PPD_TRY(degrid_dual(p, c.dual, pa));                    // step 10 argument, first Alg. 2 step
-      for (int s = 1; s < c.dual.n_itr; ++s) {
-        PPD_TRY(alg2_launch(p, 1, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb,
-                            c.dual.active));
-        std::swap(pa, pb);
-      }
-      PPD_TRY(grid_dual(p, c.dual, pa));                      // steps 10-12
-    } else {
-      PPD_TRY(degrid_plain(p, p->ybuf));
-      PPD_TRY(plain_dual(p, c.dual));                         // steps 10-11, block by block
-      PPD_TRY(grid_plain(p, c.dual.v));                       // step 12
+  if (c.sara_forked) {
+    {
+      OnStream on(p, p->aux);
+      PPD_TRY(sara_path(p, c));
+      PPD_HIP(hipEventRecord(p->ev_join, p->aux));
     }
-    PPD_TRY(fft_cols_inverse(p));
-    PPD_HIP(hipEventRecord(p->ev_join, p->aux));
+    PPD_TRY(data_path(p, c));
+  } else {
+    {
+      OnStream on(p, p->aux);
+      PPD_TRY(data_path(p, c));
+      PPD_HIP(hipEventRecord(p->ev_join, p->aux));
+    }
+    PPD_TRY(sara_path(p, c));
   }
-  PPD_TRY(sara_dual(p, xt, c.u, c.alpha, c.lambda, c.W, c.basis_active));   // steps 19-20
-  PPD_TRY(sara_synthesis(p, c.u, p->ut, c.W));              // step 21, summed over i
   PPD_HIP(hipStreamWaitEvent(p->stream, p->ev_join, 0));
   // steps 28-30, and the forward row pass of the new x~ for the next step 4
   return fft_rows_inverse_primal(p, c.primal, p->half_f);
@@ -256,6 +276,7 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   c.dual.active = prm->block_active;
   c.basis_active = prm->basis_active;
   c.n_newton = prm->n_newton == 0 ? 12 : prm->n_newton;
+  c.sara_forked = !prm->use_graph;
 
   if (n_iter > 0) {
     // the first iteration's forward row pass; each iteration then leaves
