@@ -216,12 +216,19 @@ __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float*
 // each thread makes an even / odd output pair from the same Q coefficients.
 // Rows (axis 1) first, then columns (axis 0).  sink(slot, r, c, v) receives
 // the outputs; slot counts the thread's outputs in a fixed order.
+// The low-pass band of a coefficient window taken from LDS instead of
+// memory: window entry (a, b) of the tile is p[(a + offy) * stride + b + offx].
+struct LLWin {
+  const float* p = nullptr;
+  int stride = 0, offy = 0, offx = 0;
+};
+
 template <int Q, typename Sink>
 __device__ void idwt_tile(const float* __restrict__ llsrc, int llstride, const float* __restrict__ ucoef,
                           const float* __restrict__ wcoef, const float* __restrict__ llw, int nx, int hh,
                           int ww, int y0, int x0, int tsy, int tsx, const float* __restrict__ filt,
                           float* s_ll, float* s_lh, float* s_hl, float* s_hh, float* s_a, float* s_d,
-                          Sink sink) {
+                          Sink sink, const LLWin win = LLWin{}) {
   float h[2 * Q], g[2 * Q];
   load_filt<Q>(filt, h, g);
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -241,7 +248,8 @@ __device__ void idwt_tile(const float* __restrict__ llsrc, int llstride, const f
       const size_t pll = size_t(r) * llstride + c;
       const size_t plh = size_t(r) * nx + (ow + c), phl = size_t(oh + r) * nx + c;
       const size_t phh = size_t(oh + r) * nx + (ow + c);
-      v4[k][0] = llsrc[pll] * (llw ? llw[pll] : 1.0f);
+      v4[k][0] = win.p ? win.p[(a + win.offy) * win.stride + (b + win.offx)]
+                       : llsrc[pll] * (llw ? llw[pll] : 1.0f);
       v4[k][1] = ucoef[plh] * (wcoef ? wcoef[plh] : 1.0f);
       v4[k][2] = ucoef[phl] * (wcoef ? wcoef[phl] : 1.0f);
       v4[k][3] = ucoef[phh] * (wcoef ? wcoef[phh] : 1.0f);
@@ -334,6 +342,66 @@ __global__ __launch_bounds__(256) void k_idwt(const float* __restrict__ u, float
   PPD_IDWT_SWITCH(q, llsrc, llstride, ucoef, wcoef, llw, g.nx, hh, ww, y0, x0, tsy, tsx, filt, s_ll, s_lh,
                   s_hl, s_hh, s_a, s_d, sink)
 }
+
+// The two coarsest synthesis levels L and L-1 (L >= 3) in one launch: a
+// workgroup first rebuilds, from the level-L coefficients, the window of
+// the level-(L-1) low-pass band its level-(L-1) tile reads (periodic, even
+// aligned; neighbouring workgroups recompute the overlap), keeps it in LDS,
+// then synthesises its tile of the level-(L-2) low-pass band.  One launch
+// fewer on SARA's chain of dependent launches.
+constexpr int WIN = ST / 2 + FILT_STRIDE / 2 + 2;   // LL window edge (outer window + alignment, even)
+
+template <int Q>
+__device__ void idwt2_body(const float* __restrict__ ucoef, const float* __restrict__ wcoef, float* dst,
+                           const float* __restrict__ filt, int nx, int hh, int ww, int y0, int x0, int tsy,
+                           int tsx, float* s_ll, float* s_lh, float* s_hl, float* s_hh, float* s_a, float* s_d,
+                           float* s_win) {
+  const int oh = hh >> 1, ow = ww >> 1;                      // level-(L-1) band = inner output
+  const int wy0 = (y0 >> 1) - Q, wx0 = (x0 >> 1) - Q;        // outer coefficient window origin
+  const int ya = wy0 - (wy0 & 1), xa = wx0 - (wx0 & 1);      // even-aligned inner tile origin
+  const int offy = wy0 - ya, offx = wx0 - xa;
+  const int ti_y = ((tsy >> 1) + Q + offy + 1) & ~1, ti_x = ((tsx >> 1) + Q + offx + 1) & ~1;
+  auto sink_win = [&](int, int r, int c, float v) { s_win[r * WIN + c] = v; };
+  // level L: its low-pass band and details are coefficients (in u, weighted)
+  idwt_tile<Q>(ucoef, nx, ucoef, wcoef, wcoef, nx, oh, ow, ya, xa, ti_y, ti_x, filt, s_ll, s_lh, s_hl, s_hh,
+               s_a, s_d, sink_win);
+  auto sink = [&](int, int r, int c, float v) { dst[size_t(y0 + r) * ww + (x0 + c)] = v; };
+  LLWin win;
+  win.p = s_win;
+  win.stride = WIN;
+  win.offy = offy;
+  win.offx = offx;
+  idwt_tile<Q>(nullptr, 0, ucoef, wcoef, nullptr, nx, hh, ww, y0, x0, tsy, tsx, filt, s_ll, s_lh, s_hl, s_hh,
+               s_a, s_d, sink, win);
+}
+
+__global__ __launch_bounds__(256) void k_idwt2(const float* __restrict__ u, float* __restrict__ rec,
+                                               const float* __restrict__ filt, const float* __restrict__ W,
+                                               SaraGeom g) {
+  __shared__ float s_ll[SK * SK], s_lh[SK * SK], s_hl[SK * SK], s_hh[SK * SK];
+  __shared__ float s_a[SK * ST], s_d[SK * ST];
+  __shared__ float s_win[WIN * WIN];
+  const int l = g.L - 1;                                      // outer level
+  const int hh = g.ny >> (l - 1), ww = g.nx >> (l - 1);
+  const int tsy = min(ST, hh), tsx = min(ST, ww);
+  const int y0 = blockIdx.y * tsy, x0 = blockIdx.x * tsx;
+  const int q = blockIdx.z + 1;
+  const float* ucoef = u + size_t(q) * g.N;
+  const float* wcoef = W ? W + size_t(q) * g.N : nullptr;
+  float* dst = rec + g.off[l - 1] + size_t(q - 1) * lvl_size(g, l - 1);
+  switch (q) {
+    case 1: idwt2_body<1>(ucoef, wcoef, dst, filt, g.nx, hh, ww, y0, x0, tsy, tsx, s_ll, s_lh, s_hl, s_hh, s_a, s_d, s_win); break;
+    case 2: idwt2_body<2>(ucoef, wcoef, dst, filt, g.nx, hh, ww, y0, x0, tsy, tsx, s_ll, s_lh, s_hl, s_hh, s_a, s_d, s_win); break;
+    case 3: idwt2_body<3>(ucoef, wcoef, dst, filt, g.nx, hh, ww, y0, x0, tsy, tsx, s_ll, s_lh, s_hl, s_hh, s_a, s_d, s_win); break;
+    case 4: idwt2_body<4>(ucoef, wcoef, dst, filt, g.nx, hh, ww, y0, x0, tsy, tsx, s_ll, s_lh, s_hl, s_hh, s_a, s_d, s_win); break;
+    case 5: idwt2_body<5>(ucoef, wcoef, dst, filt, g.nx, hh, ww, y0, x0, tsy, tsx, s_ll, s_lh, s_hl, s_hh, s_a, s_d, s_win); break;
+    case 6: idwt2_body<6>(ucoef, wcoef, dst, filt, g.nx, hh, ww, y0, x0, tsy, tsx, s_ll, s_lh, s_hl, s_hh, s_a, s_d, s_win); break;
+    case 7: idwt2_body<7>(ucoef, wcoef, dst, filt, g.nx, hh, ww, y0, x0, tsy, tsx, s_ll, s_lh, s_hl, s_hh, s_a, s_d, s_win); break;
+    default: idwt2_body<8>(ucoef, wcoef, dst, filt, g.nx, hh, ww, y0, x0, tsy, tsx, s_ll, s_lh, s_hl, s_hh, s_a, s_d, s_win); break;
+  }
+}
+static_assert(ST / 2 + FILT_STRIDE / 2 + 1 <= WIN && WIN <= ST, "the LL window fits an inner tile");
+static_assert(WIN / 2 + FILT_STRIDE / 2 <= SK, "the inner coefficient window fits the staging");
 
 // Level 1 for all 8 wavelet bases, plus the Dirac part, times 1/3, on a
 // STF x STF output tile.  The coefficient windows of all 8 bases are staged
@@ -532,7 +600,21 @@ int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda, 
 
 int sara_synthesis(ppd_plan* p, const float* u, float* out, const float* W) {
   const SaraGeom g = geom(p);
-  for (int l = g.L; l >= 2; --l) {
+  int top = g.L;
+  if (g.L >= 3) {
+    // levels L and L-1 in one launch
+    const int l = g.L - 1;
+    const int hh = g.ny >> (l - 1), ww = g.nx >> (l - 1);
+    const int tsy = std::min(ST, hh), tsx = std::min(ST, ww);
+    int slot;
+    PPD_TRY(timer_begin(p, KK_IDWT, &slot));
+    hipLaunchKernelGGL(k_idwt2, dim3(ww / tsx, hh / tsy, 8), dim3(256), 0, p->stream, u, p->sara_rec, p->filt,
+                       W, g);
+    PPD_HIP(hipGetLastError());
+    PPD_TRY(timer_end(p, slot));
+    top = g.L - 2;
+  }
+  for (int l = top; l >= 2; --l) {
     const int hh = g.ny >> (l - 1), ww = g.nx >> (l - 1);
     const int tsy = std::min(ST, hh), tsx = std::min(ST, ww);
     int slot;
