@@ -685,14 +685,14 @@ __global__ __launch_bounds__(FOLD_CELLS) void k_fold(const float2* __restrict__ 
   grid[size_t(ty * T + a) * Kx + (tx * T + b)] = make_float2(sx, sy);
 }
 
-// 8 x 8 tiles: one tile per workgroup, FOLD8_SPLIT threads per cell, thread
-// p taking every FOLD8_SPLIT-th slot from p (a tile's region may come from
-// dozens of items, and their loads are independent); the parts are added in
-// a fixed order.  Workgroups take the tiles in the plan's fold order: tile
-// rows spread over the XCDs, and on each XCD the tiles with the most item
-// regions first, so the longest sums start first.
+// 8 x 8 tiles: one tile per workgroup, FOLD8_SPLIT threads per cell (1 by
+// default, measured best with the fold order), thread p taking every
+// FOLD8_SPLIT-th slot from p; the parts are added in a fixed order.
+// Workgroups take the tiles in the plan's fold order: tile rows spread over
+// the XCDs, and on each XCD the tiles with the most item regions first, so
+// the longest sums start first.
 #ifndef PPD_FOLD8_SPLIT
-#define PPD_FOLD8_SPLIT 2
+#define PPD_FOLD8_SPLIT 1
 #endif
 constexpr int FOLD8_SPLIT = PPD_FOLD8_SPLIT;
 
