@@ -133,100 +133,76 @@ __global__ __launch_bounds__(256) void k_block_factors(const double* __restrict_
 // nu = 0 climbs to the root without overshooting; g'(nu) = S3 / r^3 with
 // S3 = sum a^2 / (U + nu)^3.  bfac[j].x carries nu between the passes.
 
-// Per-segment partials S2, S3 at the block's current nu (0 on the first pass).
-constexpr int SEC_WAVES = 4;
-__global__ __launch_bounds__(64 * SEC_WAVES) void k_sec_partials(
-    const Item* __restrict__ items, int n_items, const Seg* __restrict__ segs, const double2* __restrict__ w,
+// A pass runs over chunks of SEC_CHUNK consecutive plan-order points inside
+// one block (blocks are contiguous in plan order).  The first pass forms
+// a^2 = U^2 |w - y|^2 and keeps (a^2, U) per point, the later ones read only
+// that (16 bytes per point); each workgroup writes its chunk's S2, S3 at the
+// block's current nu, summed in a fixed order (deterministic).
+constexpr int SEC_THREADS = 256;
+
+template <bool FIRST>
+__global__ __launch_bounds__(SEC_THREADS) void k_sec_chunk(
+    const int32_t* __restrict__ cstart, const int32_t* __restrict__ cblock, const double2* __restrict__ w,
     const float2* __restrict__ v, const float2* __restrict__ ga, const float2* __restrict__ y,
-    const double* __restrict__ U, const double2* __restrict__ bfac, int first, double* __restrict__ p2,
-    double* __restrict__ p3) {
-  constexpr int NW = SEC_WAVES;
-  __shared__ ItemTab tab;
-  __shared__ double s2[NW][MAX_ITEM_SEGS], s3[NW][MAX_ITEM_SEGS];
-  const int ii = xcd_remap(blockIdx.x, gridDim.x);
-  if (ii >= n_items) return;
-  const Item it = items[ii];
-  const int lane = threadIdx.x & 63;
-  const int uwid = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
-  load_item_tab(it, segs, tab);
-  for (int i = threadIdx.x; i < NW * MAX_ITEM_SEGS; i += blockDim.x) {
-    (&s2[0][0])[i] = 0.0;
-    (&s3[0][0])[i] = 0.0;
-  }
-  __syncthreads();
-  const int nseg = it.seg1 - it.seg0;
-  const int total = tab.pre[nseg];
-  int sb = 0;
-  for (int bt = uwid; bt * 64 < total; bt += NW) {
-    while (bt * 64 >= tab.pre[sb + 1]) ++sb;
-    const int li = bt * 64 + lane;
-    const bool act = li < total;
-    const int sg = act ? seg_of(li, sb, tab.pre) : sb;
-    double t2 = 0.0, t3 = 0.0;
-    if (act) {
-      const int pi = tab.start[sg] + (li - tab.pre[sg]);
-      const double Ue = U[pi];
-      const double2 we = w ? w[pi] : dual_arg(v[pi], Ue, ga[pi]);
-      const float2 ye = y[pi];
-      const double nu = first ? 0.0 : bfac[tab.block[sg]].x;
+    const double* __restrict__ U, const double2* __restrict__ bfac, double2* __restrict__ aq,
+    double* __restrict__ p2, double* __restrict__ p3) {
+  __shared__ double red2[SEC_THREADS / 64], red3[SEC_THREADS / 64];
+  const int c = blockIdx.x;
+  const int i0 = cstart[c], i1 = cstart[c + 1];
+  const double nu = FIRST ? 0.0 : bfac[cblock[c]].x;
+  double t2 = 0.0, t3 = 0.0;
+#pragma unroll 4
+  for (int i = i0 + int(threadIdx.x); i < i1; i += SEC_THREADS) {
+    double a2, Ue;
+    if (FIRST) {
+      Ue = U[i];
+      const double2 we = w ? w[i] : dual_arg(v[i], Ue, ga[i]);
+      const float2 ye = y[i];
       const double dx = we.x - double(ye.x), dy = we.y - double(ye.y);
-      const double a2 = Ue * Ue * (dx * dx + dy * dy);
-      const double inv = 1.0 / (Ue + nu);
-      t2 = a2 * inv * inv;
-      t3 = t2 * inv;
+      a2 = Ue * Ue * (dx * dx + dy * dy);
+      aq[i] = make_double2(a2, Ue);
+    } else {
+      const double2 q = aq[i];
+      a2 = q.x;
+      Ue = q.y;
     }
-    const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
-    for (int ss = sb; ss <= slast; ++ss) {
-      const double a = wave_sum(act && sg == ss ? t2 : 0.0);
-      const double b = wave_sum(act && sg == ss ? t3 : 0.0);
-      if (lane == 0) {
-        s2[uwid][ss] += a;
-        s3[uwid][ss] += b;
-      }
-    }
+    const double inv = 1.0 / (Ue + nu);
+    const double s2 = a2 * inv * inv;
+    t2 += s2;
+    t3 += s2 * inv;
+  }
+  t2 = wave_sum(t2);
+  t3 = wave_sum(t3);
+  if ((threadIdx.x & 63) == 0) {
+    red2[threadIdx.x >> 6] = t2;
+    red3[threadIdx.x >> 6] = t3;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < nseg; k += blockDim.x) {
+  if (threadIdx.x == 0) {
     double a = 0.0, b = 0.0;
 #pragma unroll
-    for (int wv = 0; wv < NW; ++wv) {
-      a += s2[wv][k];
-      b += s3[wv][k];
+    for (int k = 0; k < SEC_THREADS / 64; ++k) {
+      a += red2[k];
+      b += red3[k];
     }
-    p2[it.seg0 + k] = a;
-    p3[it.seg0 + k] = b;
+    p2[c] = a;
+    p3[c] = b;
   }
 }
 
-// One Newton step per block: workgroup j sums the segment partials in a
+// One Newton step per block: workgroup j sums its chunks' partials in a
 // fixed order and updates nu_j = max(0, nu_j - g / g').
 __global__ __launch_bounds__(256) void k_sec_update(const double* __restrict__ p2, const double* __restrict__ p3,
-                                                    const int32_t* __restrict__ bids,
-                                                    const int32_t* __restrict__ boff,
+                                                    const int32_t* __restrict__ coff,
                                                     const double* __restrict__ eps, int first,
                                                     double2* __restrict__ bfac) {
   __shared__ double red2[4], red3[4];
   const int j = blockIdx.x;
-  const int c0 = boff[j], c1 = boff[j + 1];
+  const int c0 = coff[j], c1 = coff[j + 1];
   double a = 0.0, b = 0.0;
-  for (int base = c0; base < c1; base += 256 * BF_PER) {
-    int id[BF_PER];
-#pragma unroll
-    for (int k = 0; k < BF_PER; ++k) {
-      const int c = base + int(threadIdx.x) + k * 256;
-      id[k] = c < c1 ? bids[c] : -1;
-    }
-    double va[BF_PER], vb[BF_PER];
-#pragma unroll
-    for (int k = 0; k < BF_PER; ++k) {
-      va[k] = id[k] >= 0 ? p2[id[k]] : 0.0;
-      vb[k] = id[k] >= 0 ? p3[id[k]] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < BF_PER; ++k) {
-      a += va[k];
-      b += vb[k];
-    }
+  for (int c = c0 + int(threadIdx.x); c < c1; c += 256) {
+    a += p2[c];
+    b += p3[c];
   }
   a = wave_sum(a);
   b = wave_sum(b);
@@ -403,18 +379,22 @@ int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* v, const 
 
 int secular_solve(ppd_plan* p, const double2* w, const float2* v, const float2* ga, const float2* y,
                   const double* U, int n_newton) {
-  double* p2 = p->part;
-  double* p3 = p->part + p->n_segs;
+  double* p2 = p->sec_part;
+  double* p3 = p->sec_part + p->n_sec_chunks;
   for (int s = 0; s < n_newton; ++s) {
     int slot;
     PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
-    hipLaunchKernelGGL(k_sec_partials, dim3(p->n_launch), dim3(64 * SEC_WAVES), 0, p->stream, p->items,
-                       p->n_items, p->segs, w, v, ga, y, U, p->bfac, int(s == 0), p2, p3);
+    if (s == 0)
+      hipLaunchKernelGGL(k_sec_chunk<true>, dim3(p->n_sec_chunks), dim3(SEC_THREADS), 0, p->stream, p->sec_cstart,
+                         p->sec_cblock, w, v, ga, y, U, p->bfac, p->qbuf, p2, p3);
+    else
+      hipLaunchKernelGGL(k_sec_chunk<false>, dim3(p->n_sec_chunks), dim3(SEC_THREADS), 0, p->stream, p->sec_cstart,
+                         p->sec_cblock, w, v, ga, y, U, p->bfac, p->qbuf, p2, p3);
     PPD_HIP(hipGetLastError());
     PPD_TRY(timer_end(p, slot));
     PPD_TRY(timer_begin(p, KK_MISC, &slot));
-    hipLaunchKernelGGL(k_sec_update, dim3(p->d), dim3(256), 0, p->stream, p2, p3, p->bseg_ids, p->bseg_off_d,
-                       p->eps_d, int(s == 0), p->bfac);
+    hipLaunchKernelGGL(k_sec_update, dim3(p->d), dim3(256), 0, p->stream, p2, p3, p->sec_coff, p->eps_d,
+                       int(s == 0), p->bfac);
     PPD_HIP(hipGetLastError());
     PPD_TRY(timer_end(p, slot));
   }

@@ -451,6 +451,19 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
     }
   }
 
+  // chunks of the exact prox's Newton passes (SEC_CHUNK points, one block each)
+  std::vector<int32_t> cstart, cblock, coff(p->d + 1, 0);
+  for (int j = 0; j < p->d; ++j) {
+    coff[j] = int32_t(cblock.size());
+    for (int64_t s0 = p->block_off[j]; s0 < p->block_off[j + 1]; s0 += SEC_CHUNK) {
+      cstart.push_back(int32_t(s0));
+      cblock.push_back(j);
+    }
+  }
+  coff[p->d] = int32_t(cblock.size());
+  cstart.push_back(int32_t(M));
+  p->n_sec_chunks = int(cblock.size());
+
   // ---- device memory -----------------------------------------------------------
   const size_t K2 = size_t(p->Kx) * p->Ky;
   const size_t N = size_t(p->nx) * p->ny;
@@ -484,6 +497,10 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   A(dalloc(p, &p->wbuf, M));
   A(dalloc(p, &p->gabuf, M));
   A(dalloc(p, &p->qbuf, M));
+  A(dalloc(p, &p->sec_cstart, cstart.size()));
+  A(dalloc(p, &p->sec_cblock, cblock.size()));
+  A(dalloc(p, &p->sec_coff, coff.size()));
+  A(dalloc(p, &p->sec_part, 2 * cblock.size()));
   A(dalloc(p, &p->part, 2 * size_t(p->n_segs)));
   A(dalloc(p, &p->rpart, p->n_segs));
   A(dalloc(p, &p->eps_d, p->d));
@@ -519,6 +536,9 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   up(p->segs, segs.data(), sizeof(Seg) * p->n_segs);
   up(p->tile_item_off, tile_item_off.data(), 4 * (ntiles + 1));
   up(p->fold_order, fold_order.data(), 4 * fold_order.size());
+  up(p->sec_cstart, cstart.data(), 4 * cstart.size());
+  up(p->sec_cblock, cblock.data(), 4 * cblock.size());
+  up(p->sec_coff, coff.data(), 4 * coff.size());
   up(p->bseg_ids, bids.data(), 4 * p->n_segs);
   up(p->bseg_off_d, p->bseg_off.data(), 4 * (p->d + 1));
   up(p->vis_block, vblk.data(), 4 * M);

@@ -34,6 +34,7 @@ constexpr int KB_DEG = 9;         // polynomial degree per tap
 constexpr int KB_NC = KB_DEG + 1; // coefficients per tap
 constexpr int N_BASES = 9;        // Dirac + db1..db8
 constexpr int FILT_STRIDE = 16;   // max Daubechies taps (db8)
+constexpr int SEC_CHUNK = 2048;   // points per workgroup of an exact-prox Newton pass
 constexpr int MAX_ITEM_SEGS = 64; // per-block segments of one work item (one wave scans them)
 constexpr int MAX_XCD = 8;
 
@@ -115,7 +116,14 @@ struct ppd_plan {
   float2* ybuf = nullptr;                  // [M] complex64 scratch
   double2* wbuf = nullptr;                 // [M] complex128 w (plain form)
   float2* gabuf = nullptr;                 // [M] complex64 Theta G a (fused form; w is rebuilt from it)
-  double2* qbuf = nullptr;                 // [M] complex128 (plain form)
+  double2* qbuf = nullptr;                 // [M] complex128 (plain form; (a^2, U) of the Newton passes)
+  // Newton passes of the exact prox: chunks of consecutive plan-order
+  // visibilities inside one block
+  int n_sec_chunks = 0;
+  int32_t* sec_cstart = nullptr;           // [n_sec_chunks + 1] first visibility of each chunk
+  int32_t* sec_cblock = nullptr;           // [n_sec_chunks] block of each chunk
+  int32_t* sec_coff = nullptr;             // [d + 1] chunks of block j: [sec_coff[j], sec_coff[j+1])
+  double* sec_part = nullptr;              // [2][n_sec_chunks] S2, S3 partials
   double* part = nullptr;                  // [2][n_segs] block-norm partials
   double* rpart = nullptr;                 // [n_segs] residual partials
   double* eps_d = nullptr;                 // [d]

@@ -148,3 +148,36 @@ def test_many_blocks_per_tile(tile):
     P.ppd_iterate(plan, st, y, U, pb.eps, 3, eta=pb.eta, mu=1.0, n_itr=2)
     assert_op_close(host(st.x), ost.x, what="x")
     assert_op_close(host(st.z), ost.z[perm], what="z")
+
+
+def test_per_kernel_timing_counts():
+    """The per-launch event timer sees every launch of eager iterations (both
+    streams) with the expected counts per kind, and none inside a captured
+    graph (only the call's first row pass runs outside it)."""
+    P = require_gpu()
+    import torch
+    announce("per-kernel timing")
+    pb, wu, wv = _small_problem()
+    n = pb.x_true.shape[0]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = P.Plan(n, n, wu, wv, pb.block_off, stream=stream)
+        perm, y, U = _gpu_inputs(P, plan, pb)
+        st = P.PPDState(plan, y)
+        plan.timing(True)
+        plan.timing_reset()
+        P.ppd_iterate(plan, st, y, U, pb.eps, 3, eta=pb.eta, mu=1.0, stats=False)
+        t = plan.timing_read()
+        per_iter = {"fft_cols_fwd": 1, "degrid": 1, "grid": 1, "fold": 1, "fft_cols_inv": 1, "fft_rows_inv": 1,
+                    "dwt": 3, "idwt": 2}   # levels 3: two coarsest synthesis levels in one launch + last
+        for k, c in per_iter.items():
+            assert t[k][0] == 3 * c, (k, t[k])
+            assert t[k][1] > 0.0, (k, t[k])
+        assert t["fft_rows_fwd"][0] == 1   # the first iteration's row pass; later ones are fused
+        plan.timing_reset()
+        P.ppd_iterate(plan, st, y, U, pb.eps, 3, eta=pb.eta, mu=1.0, stats=False, use_graph=True)
+        t = plan.timing_read()
+        plan.timing(False)
+        stream.synchronize()
+    assert t.get("fft_rows_fwd", (0, 0.0))[0] == 1
+    assert all(t.get(k, (0, 0.0))[0] == 0 for k in per_iter), t
