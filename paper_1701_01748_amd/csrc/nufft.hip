@@ -498,6 +498,158 @@ __device__ __forceinline__ void tab_from_seg(const Seg& sg, int lane, ItemTab& t
   if (lane == 0) tab.pre[0] = 0;
 }
 
+// Degridding of 8 x 8 tiles by single-wave workgroups that each take a run
+// of PPD_DEGRID_RUN consecutive items (0: one item per workgroup, k_degrid).
+// The next item's region and segment list are loaded into registers while
+// the current item is worked on; per-segment sums are kept by the lane of
+// the segment (same order as k_degrid's).
+#ifndef PPD_DEGRID_RUN
+#define PPD_DEGRID_RUN 2
+#endif
+template <bool DUAL>
+__global__ __launch_bounds__(64) void k_degrid8(
+    const float2* __restrict__ grid, int Kx, int Ky, const Item* __restrict__ items, int n_items,
+    const Seg* __restrict__ segs, const float* __restrict__ wu, const float* __restrict__ wv,
+    const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
+    float2* __restrict__ out, const float2* __restrict__ y, const double* __restrict__ U,
+    const float2* __restrict__ v, const double2* __restrict__ z, float2* __restrict__ gout, double mu,
+    double* __restrict__ part, double* __restrict__ rpart) {
+  constexpr int T = 8, R = T + 7, RUN = PPD_DEGRID_RUN > 0 ? PPD_DEGRID_RUN : 1;
+  constexpr int RPT = (R * R + 63) / 64;
+  static_assert(RUN <= 64, "a run's items are held one per lane");
+  __shared__ float2 reg[R * R];
+  __shared__ ItemTab tab;
+  const int i0 = xcd_remap(blockIdx.x, gridDim.x) * RUN;
+  if (i0 >= n_items) return;
+  const int i1 = min(i0 + RUN, n_items);
+  const int lane = threadIdx.x;
+  Item itl{0, 0, 0, 0};
+  if (i0 + lane < i1) itl = items[i0 + lane];
+  auto field = [&](int f, int i) { return __builtin_amdgcn_readlane(f, i - i0); };
+  float2 gv[RPT];
+  auto region = [&](int i) {
+    const int r0 = field(itl.ty, i) * T, c0 = field(itl.tx, i) * T;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int e = lane + k * 64;
+      if (e < R * R) {
+        const int a = e / R, b = e - a * R;
+        gv[k] = grid[size_t((r0 + a) & (Ky - 1)) * Kx + ((c0 + b) & (Kx - 1))];
+      }
+    }
+  };
+  region(i0);
+  Seg sgn = item_seg(segs, field(itl.seg0, i0), field(itl.seg1, i0), lane);
+  KbCoef kbw;
+  load_kb(kbc, kbw);
+  struct Batch {
+    float ou, ov, th;
+    float2 v, y;
+    double2 z;
+    double U;
+    int pi, sg, sb;
+  };
+  for (int cur = i0; cur < i1; ++cur) {
+    // the previous item's LDS reads are done (program order within the wave)
+    tab_from_seg(sgn, lane, tab);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+      if (lane + k * 64 < R * R) reg[lane + k * 64] = gv[k];
+    __builtin_amdgcn_wave_barrier();
+    const int r0 = field(itl.ty, cur) * T, c0 = field(itl.tx, cur) * T;
+    const int seg0 = field(itl.seg0, cur), nseg = field(itl.seg1, cur) - seg0;
+    const int total = __builtin_amdgcn_readfirstlane(tab.pre[nseg]);
+    auto load = [&](int bt, int& sb, Batch& b) {
+      while (bt * 64 >= tab.pre[sb + 1]) ++sb;
+      b.sb = sb;
+      const int li = bt * 64 + lane;
+      b.sg = sb;
+      if (li < total) {
+        b.sg = seg_of(li, sb, tab.pre);
+        b.pi = tab.start[b.sg] + (li - tab.pre[b.sg]);
+        b.ou = wu[b.pi];
+        b.ov = wv[b.pi];
+        b.th = theta ? theta[b.pi] : 1.0f;
+        if (DUAL) {
+          b.v = v[b.pi];
+          b.U = U[b.pi];
+          b.z = z[b.pi];
+          b.y = y[b.pi];
+        }
+      }
+    };
+    int sbl = 0;
+    Batch bn{};
+    if (total > 0) load(0, sbl, bn);
+    // the next item's region and segments, behind this item's first batch
+    if (cur + 1 < i1) {
+      region(cur + 1);
+      sgn = item_seg(segs, field(itl.seg0, cur + 1), field(itl.seg1, cur + 1), lane);
+    }
+    double q_acc = 0.0, r_acc = 0.0;   // lane s: segment s of the item
+    for (int bt = 0; bt * 64 < total; ++bt) {
+      const Batch cb = bn;
+      if ((bt + 1) * 64 < total) load(bt + 1, sbl, bn);
+      const int li = bt * 64 + lane;
+      const bool act = li < total;
+      const int sb = __builtin_amdgcn_readfirstlane(cb.sb), sg = cb.sg, pi = cb.pi;
+      double qn = 0.0, rn = 0.0;
+      if (act) {
+        Taps t;
+        taps_for<T>(cb.ou, cb.ov, su, sv, Kx, Ky, c0, r0, kbw.c, t);
+        float ax = 0.f, ay = 0.f;
+#pragma unroll
+        for (int a = 0; a < KB_TAPS; ++a) {
+          const float2* row = reg + (t.ov + a) * R + t.ou;
+          float sx = 0.f, sy = 0.f;
+#pragma unroll
+          for (int b = 0; b < KB_TAPS; ++b) {
+            const float2 g = row[b];
+            sx = fmaf(t.wx[b], g.x, sx);
+            sy = fmaf(t.wx[b], g.y, sy);
+          }
+          const float wya = a == 0 ? t.wy[0] : a == 1 ? t.wy[1] : a == 2 ? t.wy[2] : a == 3 ? t.wy[3]
+                          : a == 4 ? t.wy[4] : a == 5 ? t.wy[5] : a == 6 ? t.wy[6] : t.wy[7];
+          ax = fmaf(wya, sx, ax);
+          ay = fmaf(wya, sy, ay);
+        }
+        const float2 g = make_float2(ax * cb.th, ay * cb.th);
+        if (!DUAL) {
+          out[pi] = g;
+        } else {
+          // Algorithm 3 step 10 argument and the first Algorithm 2 step, as
+          // in k_degrid
+          gout[pi] = g;
+          const double Ue = cb.U;
+          const double2 we = dual_arg(cb.v, Ue, g), ze = cb.z;
+          const double mU = mu * Ue;
+          const double dx = (ze.x - mU * (ze.x - we.x)) - double(cb.y.x);
+          const double dy = (ze.y - mU * (ze.y - we.y)) - double(cb.y.y);
+          qn = dx * dx + dy * dy;
+          const double ex = double(g.x) - double(cb.y.x), ey = double(g.y) - double(cb.y.y);
+          rn = ex * ex + ey * ey;
+        }
+      }
+      if (DUAL) {
+        const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
+        for (int ss = sb; ss <= slast; ++ss) {
+          const double a = wave_sum(act && sg == ss ? qn : 0.0);
+          const double r = wave_sum(act && sg == ss ? rn : 0.0);
+          if (lane == ss) {
+            q_acc += a;
+            r_acc += r;
+          }
+        }
+      }
+    }
+    if (DUAL && lane < nseg) {
+      part[seg0 + lane] = q_acc;
+      rpart[seg0 + lane] = r_acc;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 template <bool DUAL>
 __global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
     float2* __restrict__ scratch, int Kx, int Ky, const Item* __restrict__ items, int n_items,
@@ -757,8 +909,27 @@ __global__ void k_permute(const int32_t* __restrict__ perm, int64_t M, int to_us
   }
 }
 
+// workgroups of the 8 x 8 degridding in runs: a multiple of the XCD count
+int degrid8_launch(const ppd_plan* p) {
+  constexpr int run = PPD_DEGRID_RUN > 0 ? PPD_DEGRID_RUN : 1;
+  const int wgs = (p->n_items + run - 1) / run;
+  return ((wgs + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
+}
+
 template <int T>
 int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double* part_out) {
+  if (T == 8 && PPD_DEGRID_RUN > 0) {
+    if (!dual)
+      hipLaunchKernelGGL((k_degrid8<false>), dim3(degrid8_launch(p)), dim3(64), 0, p->stream, p->grid_f, p->Kx,
+                         p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale, p->sv_scale,
+                         p->kbc, out, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr);
+    else
+      hipLaunchKernelGGL((k_degrid8<true>), dim3(degrid8_launch(p)), dim3(64), 0, p->stream, p->grid_f, p->Kx,
+                         p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale, p->sv_scale,
+                         p->kbc, nullptr, a->y, a->U, a->v, a->z, p->gabuf, a->mu, part_out, p->rpart);
+    PPD_HIP(hipGetLastError());
+    return PPD_OK;
+  }
   if (!dual) {
     hipLaunchKernelGGL((k_degrid<T, false>), dim3(p->n_launch), dim3(64 * DegridCfg<T>::NW), 0, p->stream, p->grid_f,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
