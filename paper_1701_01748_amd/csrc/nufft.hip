@@ -498,20 +498,20 @@ __device__ __forceinline__ void tab_from_seg(const Seg& sg, int lane, ItemTab& t
   if (lane == 0) tab.pre[0] = 0;
 }
 
-// Degridding of 8 x 8 tiles by single-wave workgroups that each take a run
-// of PPD_DEGRID_RUN consecutive items (0: one item per workgroup, k_degrid).
+// Degridding of 8 x 8 tiles with the dual update by single-wave workgroups
+// that each take a run of PPD_DEGRID_RUN consecutive items (0: one item per
+// workgroup, k_degrid, which also serves plain Phi).
 // The next item's region and segment list are loaded into registers while
 // the current item is worked on; per-segment sums are kept by the lane of
 // the segment (same order as k_degrid's).
 #ifndef PPD_DEGRID_RUN
 #define PPD_DEGRID_RUN 2
 #endif
-template <bool DUAL>
 __global__ __launch_bounds__(64) void k_degrid8(
     const float2* __restrict__ grid, int Kx, int Ky, const Item* __restrict__ items, int n_items,
     const Seg* __restrict__ segs, const float* __restrict__ wu, const float* __restrict__ wv,
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
-    float2* __restrict__ out, const float2* __restrict__ y, const double* __restrict__ U,
+    const float2* __restrict__ y, const double* __restrict__ U,
     const float2* __restrict__ v, const double2* __restrict__ z, float2* __restrict__ gout, double mu,
     double* __restrict__ part, double* __restrict__ rpart) {
   constexpr int T = 8, R = T + 7, RUN = PPD_DEGRID_RUN > 0 ? PPD_DEGRID_RUN : 1;
@@ -570,12 +570,10 @@ __global__ __launch_bounds__(64) void k_degrid8(
         b.ou = wu[b.pi];
         b.ov = wv[b.pi];
         b.th = theta ? theta[b.pi] : 1.0f;
-        if (DUAL) {
-          b.v = v[b.pi];
-          b.U = U[b.pi];
-          b.z = z[b.pi];
-          b.y = y[b.pi];
-        }
+        b.v = v[b.pi];
+        b.U = U[b.pi];
+        b.z = z[b.pi];
+        b.y = y[b.pi];
       }
     };
     int sbl = 0;
@@ -613,36 +611,30 @@ __global__ __launch_bounds__(64) void k_degrid8(
           ax = fmaf(wya, sx, ax);
           ay = fmaf(wya, sy, ay);
         }
+        // Algorithm 3 step 10 argument and the first Algorithm 2 step, as in
+        // k_degrid
         const float2 g = make_float2(ax * cb.th, ay * cb.th);
-        if (!DUAL) {
-          out[pi] = g;
-        } else {
-          // Algorithm 3 step 10 argument and the first Algorithm 2 step, as
-          // in k_degrid
-          gout[pi] = g;
-          const double Ue = cb.U;
-          const double2 we = dual_arg(cb.v, Ue, g), ze = cb.z;
-          const double mU = mu * Ue;
-          const double dx = (ze.x - mU * (ze.x - we.x)) - double(cb.y.x);
-          const double dy = (ze.y - mU * (ze.y - we.y)) - double(cb.y.y);
-          qn = dx * dx + dy * dy;
-          const double ex = double(g.x) - double(cb.y.x), ey = double(g.y) - double(cb.y.y);
-          rn = ex * ex + ey * ey;
-        }
+        gout[pi] = g;
+        const double Ue = cb.U;
+        const double2 we = dual_arg(cb.v, Ue, g), ze = cb.z;
+        const double mU = mu * Ue;
+        const double dx = (ze.x - mU * (ze.x - we.x)) - double(cb.y.x);
+        const double dy = (ze.y - mU * (ze.y - we.y)) - double(cb.y.y);
+        qn = dx * dx + dy * dy;
+        const double ex = double(g.x) - double(cb.y.x), ey = double(g.y) - double(cb.y.y);
+        rn = ex * ex + ey * ey;
       }
-      if (DUAL) {
-        const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
-        for (int ss = sb; ss <= slast; ++ss) {
-          const double a = wave_sum(act && sg == ss ? qn : 0.0);
-          const double r = wave_sum(act && sg == ss ? rn : 0.0);
-          if (lane == ss) {
-            q_acc += a;
-            r_acc += r;
-          }
+      const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
+      for (int ss = sb; ss <= slast; ++ss) {
+        const double a = wave_sum(act && sg == ss ? qn : 0.0);
+        const double r = wave_sum(act && sg == ss ? rn : 0.0);
+        if (lane == ss) {
+          q_acc += a;
+          r_acc += r;
         }
       }
     }
-    if (DUAL && lane < nseg) {
+    if (lane < nseg) {
       part[seg0 + lane] = q_acc;
       rpart[seg0 + lane] = r_acc;
     }
@@ -918,15 +910,12 @@ int degrid8_launch(const ppd_plan* p) {
 
 template <int T>
 int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double* part_out) {
-  if (T == 8 && PPD_DEGRID_RUN > 0) {
-    if (!dual)
-      hipLaunchKernelGGL((k_degrid8<false>), dim3(degrid8_launch(p)), dim3(64), 0, p->stream, p->grid_f, p->Kx,
-                         p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale, p->sv_scale,
-                         p->kbc, out, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr);
-    else
-      hipLaunchKernelGGL((k_degrid8<true>), dim3(degrid8_launch(p)), dim3(64), 0, p->stream, p->grid_f, p->Kx,
-                         p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale, p->sv_scale,
-                         p->kbc, nullptr, a->y, a->U, a->v, a->z, p->gabuf, a->mu, part_out, p->rpart);
+  // runs for the fused dual pass only: plain Phi is faster one item per
+  // workgroup (27.4 against 29.7 us at 512^2, M = 1.3M)
+  if (T == 8 && PPD_DEGRID_RUN > 0 && dual) {
+    hipLaunchKernelGGL(k_degrid8, dim3(degrid8_launch(p)), dim3(64), 0, p->stream, p->grid_f, p->Kx, p->Ky,
+                       p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale, p->sv_scale, p->kbc,
+                       a->y, a->U, a->v, a->z, p->gabuf, a->mu, part_out, p->rpart);
     PPD_HIP(hipGetLastError());
     return PPD_OK;
   }
