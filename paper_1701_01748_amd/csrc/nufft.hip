@@ -77,6 +77,56 @@ struct DegridCfg {
 // per-segment partials of ||q - y||^2 and ||G a - y||^2 are wave sums over
 // the lanes of each segment, added per wave in batch order and summed over
 // the waves in a fixed order at the end: deterministic.
+// 8 x 8 tiles: the 15 x 15 region is staged twice in LDS with a row stride
+// of G8_RS float2 (16-byte aligned rows), copy E holding cell (r, c) at
+// r G8_RS + c and copy O holding cell (r, c + 1) there, so that a lane's 8
+// consecutive cells of a tap row start at an even float2 of one copy and
+// are read as four 16-byte loads (half the LDS instructions of 8-byte
+// loads).  The weighted sums run in the same order as the 8-byte form.
+#ifndef PPD_DEGRID_B128
+#define PPD_DEGRID_B128 1
+#endif
+constexpr int G8_RS = 18;
+constexpr int G8_COPY = 15 * G8_RS;   // float2 per copy
+
+__device__ __forceinline__ void stage8(float2* reg2, int e, float2 g) {
+  const int a = e / 15, b = e - a * 15;
+  reg2[a * G8_RS + b] = g;
+  if (b > 0) reg2[G8_COPY + a * G8_RS + b - 1] = g;
+}
+
+__device__ __forceinline__ float2 gather8(const float2* reg2, const Taps& t) {
+  const float2* base = (t.ou & 1) ? reg2 + G8_COPY + t.ov * G8_RS + (t.ou - 1) : reg2 + t.ov * G8_RS + t.ou;
+  float ax = 0.f, ay = 0.f;
+#pragma unroll
+  for (int a = 0; a < KB_TAPS; ++a) {
+    const float4* row = reinterpret_cast<const float4*>(base + a * G8_RS);
+    const float4 q0 = row[0], q1 = row[1], q2 = row[2], q3 = row[3];
+    float sx = 0.f, sy = 0.f;
+    sx = fmaf(t.wx[0], q0.x, sx);
+    sy = fmaf(t.wx[0], q0.y, sy);
+    sx = fmaf(t.wx[1], q0.z, sx);
+    sy = fmaf(t.wx[1], q0.w, sy);
+    sx = fmaf(t.wx[2], q1.x, sx);
+    sy = fmaf(t.wx[2], q1.y, sy);
+    sx = fmaf(t.wx[3], q1.z, sx);
+    sy = fmaf(t.wx[3], q1.w, sy);
+    sx = fmaf(t.wx[4], q2.x, sx);
+    sy = fmaf(t.wx[4], q2.y, sy);
+    sx = fmaf(t.wx[5], q2.z, sx);
+    sy = fmaf(t.wx[5], q2.w, sy);
+    sx = fmaf(t.wx[6], q3.x, sx);
+    sy = fmaf(t.wx[6], q3.y, sy);
+    sx = fmaf(t.wx[7], q3.z, sx);
+    sy = fmaf(t.wx[7], q3.w, sy);
+    const float wya = a == 0 ? t.wy[0] : a == 1 ? t.wy[1] : a == 2 ? t.wy[2] : a == 3 ? t.wy[3]
+                    : a == 4 ? t.wy[4] : a == 5 ? t.wy[5] : a == 6 ? t.wy[6] : t.wy[7];
+    ax = fmaf(wya, sx, ax);
+    ay = fmaf(wya, sy, ay);
+  }
+  return make_float2(ax, ay);
+}
+
 template <int T, bool DUAL>
 __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
     const float2* __restrict__ grid, int Kx, int Ky, const Item* __restrict__ items, int n_items,
@@ -87,7 +137,8 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
     double* __restrict__ part, double* __restrict__ rpart) {
   constexpr int R = T + 7;
   constexpr int NW = DegridCfg<T>::NW;
-  __shared__ float2 reg[R * R];
+  constexpr bool B128 = PPD_DEGRID_B128 && T == 8;
+  __shared__ __align__(16) float2 reg[B128 ? 2 * G8_COPY : R * R];
   __shared__ ItemTab tab;
   __shared__ double s_q[NW][MAX_ITEM_SEGS], s_r[NW][MAX_ITEM_SEGS];
   const int ii = xcd_remap(blockIdx.x, gridDim.x);
@@ -118,7 +169,10 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int i = threadIdx.x + k * 64 * NW;
-    if (i < R * R) reg[i] = gv[k];
+    if (i < R * R) {
+      if constexpr (B128) stage8(reg, i, gv[k]);
+      else reg[i] = gv[k];
+    }
   }
   __syncthreads();
   const int nseg = it.seg1 - it.seg0;
@@ -169,20 +223,26 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
       Taps t;
       taps_for<T>(omu, omv, su, sv, Kx, Ky, c0, r0, kbw.c, t);
       float ax = 0.f, ay = 0.f;
+      if constexpr (B128) {
+        const float2 s2 = gather8(reg, t);
+        ax = s2.x;
+        ay = s2.y;
+      } else {
 #pragma unroll
-      for (int a = 0; a < KB_TAPS; ++a) {
-        const float2* row = reg + (t.ov + a) * R + t.ou;
-        float sx = 0.f, sy = 0.f;
+        for (int a = 0; a < KB_TAPS; ++a) {
+          const float2* row = reg + (t.ov + a) * R + t.ou;
+          float sx = 0.f, sy = 0.f;
 #pragma unroll
-        for (int b = 0; b < KB_TAPS; ++b) {
-          const float2 g = row[b];
-          sx = fmaf(t.wx[b], g.x, sx);
-          sy = fmaf(t.wx[b], g.y, sy);
+          for (int b = 0; b < KB_TAPS; ++b) {
+            const float2 g = row[b];
+            sx = fmaf(t.wx[b], g.x, sx);
+            sy = fmaf(t.wx[b], g.y, sy);
+          }
+          const float wya = a == 0 ? t.wy[0] : a == 1 ? t.wy[1] : a == 2 ? t.wy[2] : a == 3 ? t.wy[3]
+                          : a == 4 ? t.wy[4] : a == 5 ? t.wy[5] : a == 6 ? t.wy[6] : t.wy[7];
+          ax = fmaf(wya, sx, ax);
+          ay = fmaf(wya, sy, ay);
         }
-        const float wya = a == 0 ? t.wy[0] : a == 1 ? t.wy[1] : a == 2 ? t.wy[2] : a == 3 ? t.wy[3]
-                        : a == 4 ? t.wy[4] : a == 5 ? t.wy[5] : a == 6 ? t.wy[6] : t.wy[7];
-        ax = fmaf(wya, sx, ax);
-        ay = fmaf(wya, sy, ay);
       }
       const float2 g = make_float2(ax * th, ay * th);
       if (!DUAL) {
@@ -595,6 +655,8 @@ __global__ __launch_bounds__(64) void k_degrid8(
       if (act) {
         Taps t;
         taps_for<T>(cb.ou, cb.ov, su, sv, Kx, Ky, c0, r0, kbw.c, t);
+        // 8-byte gathers: the 16-byte form of k_degrid took this kernel to
+        // 158 VGPRs (3 waves per SIMD) and was not faster here
         float ax = 0.f, ay = 0.f;
 #pragma unroll
         for (int a = 0; a < KB_TAPS; ++a) {
