@@ -81,6 +81,18 @@ typedef struct {
  * and allocates the plan's work buffers.  Synchronous.  `stream` is a
  * hipStream_t (NULL = default stream) used by every later call. */
 int ppd_plan_create(ppd_plan** plan, const ppd_plan_desc* desc, void* stream);
+
+/* The same plan with every device buffer carved from a caller-owned
+ * workspace, so that the caller's allocator (PyTorch) is the only one.
+ * ppd_plan_workspace_size runs the host part of plan creation (validation
+ * and binning, no HIP call) and returns the bytes needed; ppd_plan_create_ws
+ * takes a DEVICE workspace of at least that size, 256-byte aligned, which
+ * must stay allocated and untouched until ppd_plan_destroy (which does not
+ * free it).  Errors: PPD_EINVAL for a NULL, misaligned or too small
+ * workspace, else as ppd_plan_create. */
+int ppd_plan_workspace_size(const ppd_plan_desc* desc, size_t* bytes /* HOST */);
+int ppd_plan_create_ws(ppd_plan** plan, const ppd_plan_desc* desc, void* workspace, size_t bytes,
+                       void* stream);
 int ppd_plan_destroy(ppd_plan* plan);
 int ppd_plan_set_stream(ppd_plan* plan, void* stream);
 
@@ -90,7 +102,8 @@ typedef struct {
   int32_t d, levels, tile, chunk;
   int32_t n_chunks;           /* work chunks (one workgroup each)               */
   double kb_beta;
-  size_t device_bytes;        /* device memory owned by the plan                */
+  size_t device_bytes;        /* device memory of the plan's buffers (allocated,
+                                 or carved from the caller's workspace)         */
 } ppd_plan_info;
 int ppd_plan_get_info(const ppd_plan* plan, ppd_plan_info* info /* HOST */);
 

@@ -186,9 +186,22 @@ static int ilog2(int64_t v) {
   return l;
 }
 
+constexpr size_t WS_ALIGN = 256;
+
 template <typename T>
 static int dalloc(ppd_plan* p, T** ptr, size_t count) {
   if (count == 0) count = 1;
+  if (p->ws || p->ws_measure) {
+    const size_t off = (p->ws_used + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN;
+    p->ws_used = off + sizeof(T) * count;
+    p->device_bytes += sizeof(T) * count;
+    *ptr = nullptr;
+    if (p->ws_measure) return PPD_OK;
+    if (p->ws_used > p->ws_bytes)
+      return fail(PPD_EINVAL, "workspace of " + std::to_string(p->ws_bytes) + " bytes is too small");
+    *ptr = reinterpret_cast<T*>(p->ws + off);
+    return PPD_OK;
+  }
   void* q = nullptr;
   if (hipMalloc(&q, sizeof(T) * count) != hipSuccess)
     return fail(PPD_ENOMEM, "hipMalloc of " + std::to_string(sizeof(T) * count) + " bytes failed");
@@ -243,7 +256,13 @@ int ppd_daubechies_host(int p, double* h) {
   return PPD_OK;
 }
 
-int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
+}  // extern "C"
+
+// Plan creation.  With `measure` set, only the host work runs and the device
+// bytes the plan needs are returned there (no HIP call); with a workspace the
+// device buffers are carved from it, else they are allocated.
+static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, void* workspace,
+                       size_t ws_bytes, size_t* measure) {
   if (!out || !desc) return fail(PPD_EINVAL, "ppd_plan_create: NULL argument");
   *out = nullptr;
   const ppd_plan_desc& D = *desc;
@@ -292,9 +311,10 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   p->su_scale = double(p->Kx) / (2.0 * M_PI);
   p->sv_scale = double(p->Ky) / (2.0 * M_PI);
   p->has_theta = D.theta != nullptr;
-  p->stream = static_cast<hipStream_t>(stream);
   p->block_off.assign(D.block_off, D.block_off + D.d + 1);
-  (void)hipGetDevice(&p->device);
+  p->ws = static_cast<char*>(workspace);
+  p->ws_bytes = ws_bytes;
+  p->ws_measure = measure != nullptr;
 
   // ---- binning: counting sort by tile inside every block -------------------
   const int64_t M = D.M;
@@ -520,6 +540,13 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   A(dalloc(p, &p->pl_scalar, 4));
   A(dalloc(p, &p->icount, N));
   A(dalloc(p, &p->imin, 1));
+  if (measure) {
+    *measure = (p->ws_used + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN;
+    destroy_plan(p);
+    return st;
+  }
+  p->stream = static_cast<hipStream_t>(stream);
+  (void)hipGetDevice(&p->device);
   if (st != PPD_OK) {
     destroy_plan(p);
     return st;
@@ -560,6 +587,28 @@ int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
   }
   *out = p;
   return PPD_OK;
+}
+
+extern "C" {
+
+int ppd_plan_create(ppd_plan** out, const ppd_plan_desc* desc, void* stream) {
+  return create_plan(out, desc, stream, nullptr, 0, nullptr);
+}
+
+int ppd_plan_workspace_size(const ppd_plan_desc* desc, size_t* bytes) {
+  if (!bytes) return fail(PPD_EINVAL, "ppd_plan_workspace_size: NULL bytes");
+  *bytes = 0;
+  ppd_plan* unused = nullptr;
+  return create_plan(&unused, desc, nullptr, nullptr, 0, bytes);
+}
+
+int ppd_plan_create_ws(ppd_plan** out, const ppd_plan_desc* desc, void* workspace, size_t bytes, void* stream) {
+  if (!out) return fail(PPD_EINVAL, "ppd_plan_create_ws: NULL plan");
+  *out = nullptr;
+  if (!workspace) return fail(PPD_EINVAL, "ppd_plan_create_ws: NULL workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN)
+    return fail(PPD_EINVAL, "ppd_plan_create_ws: workspace must be 256-byte aligned");
+  return create_plan(out, desc, stream, workspace, bytes, nullptr);
 }
 
 int ppd_plan_destroy(ppd_plan* plan) {

@@ -142,7 +142,12 @@ struct ppd_plan {
   int32_t* imin = nullptr;                 // [1]
   size_t sara_ll_floats = 0;
   size_t device_bytes = 0;
-  std::vector<void*> allocations;
+  std::vector<void*> allocations;          // hipMalloc'd buffers (plans without a workspace)
+  // caller-owned workspace the buffers are carved from (256-byte aligned
+  // offsets), or a sizing pass that only adds up the bytes
+  char* ws = nullptr;
+  size_t ws_bytes = 0, ws_used = 0;
+  bool ws_measure = false;
 
   // graph replay of one iteration
   hipGraphExec_t graph_exec = nullptr;

@@ -65,6 +65,9 @@ _PROTOS = {
     "ppd_strerror": (ctypes.c_char_p, [c_int32]),
     "ppd_last_error": (ctypes.c_char_p, []),
     "ppd_plan_create": (c_int32, [ctypes.POINTER(c_void_p), ctypes.POINTER(PlanDesc), c_void_p]),
+    "ppd_plan_workspace_size": (c_int32, [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_size_t)]),
+    "ppd_plan_create_ws": (c_int32, [ctypes.POINTER(c_void_p), ctypes.POINTER(PlanDesc), c_void_p,
+                                     ctypes.c_size_t, c_void_p]),
     "ppd_plan_destroy": (c_int32, [c_void_p]),
     "ppd_plan_set_stream": (c_int32, [c_void_p, c_void_p]),
     "ppd_plan_get_info": (c_int32, [c_void_p, ctypes.POINTER(PlanInfo)]),
@@ -152,11 +155,31 @@ def _need(t, dtype, numel: int, name: str):
         raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
 
 
+def plan_workspace_size(nx: int, ny: int, omega_u, omega_v, block_off, theta=None, kb_beta: float = 0.0,
+                        levels: int = 3, tile: int = 0, chunk: int = 0) -> int:
+    """Device bytes a plan of this coverage needs in a caller workspace (host
+    only: validation and binning, no device call)."""
+    L = lib()
+    wu = np.ascontiguousarray(omega_u, dtype=np.float32)
+    wv = np.ascontiguousarray(omega_v, dtype=np.float32)
+    off = np.ascontiguousarray(block_off, dtype=np.int64)
+    th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float32)
+    desc = PlanDesc(nx, ny, wu.size, off.size - 1, off.ctypes.data_as(ctypes.POINTER(c_int64)),
+                    wu.ctypes.data, wv.ctypes.data, None if th is None else th.ctypes.data,
+                    kb_beta, levels, tile, chunk)
+    size = ctypes.c_size_t(0)
+    _check("ppd_plan_workspace_size", L.ppd_plan_workspace_size(ctypes.byref(desc), ctypes.byref(size)))
+    return int(size.value)
+
+
 class Plan:
-    """A libppd plan for one coverage (HOST numpy inputs, see ppd_plan_desc)."""
+    """A libppd plan for one coverage (HOST numpy inputs, see ppd_plan_desc).
+    With `workspace` (the default) the plan's device buffers live in one
+    uint8 tensor allocated here by PyTorch and kept with the plan; without
+    it the library allocates them."""
 
     def __init__(self, nx: int, ny: int, omega_u, omega_v, block_off, theta=None, kb_beta: float = 0.0,
-                 levels: int = 3, tile: int = 0, chunk: int = 0, stream=None):
+                 levels: int = 3, tile: int = 0, chunk: int = 0, stream=None, workspace: bool = True):
         import torch
         L = lib()
         self._wu = np.ascontiguousarray(omega_u, dtype=np.float32)
@@ -176,8 +199,17 @@ class Plan:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = c_void_p()
-        _check("ppd_plan_create", L.ppd_plan_create(ctypes.byref(h), ctypes.byref(desc),
-                                                    c_void_p(int(stream.cuda_stream))))
+        self._ws = None
+        if workspace:
+            size = ctypes.c_size_t(0)
+            _check("ppd_plan_workspace_size", L.ppd_plan_workspace_size(ctypes.byref(desc), ctypes.byref(size)))
+            self._ws = torch.empty(size.value, dtype=torch.uint8, device="cuda")
+            _check("ppd_plan_create_ws", L.ppd_plan_create_ws(ctypes.byref(h), ctypes.byref(desc),
+                                                              c_void_p(self._ws.data_ptr()), size,
+                                                              c_void_p(int(stream.cuda_stream))))
+        else:
+            _check("ppd_plan_create", L.ppd_plan_create(ctypes.byref(h), ctypes.byref(desc),
+                                                        c_void_p(int(stream.cuda_stream))))
         self._h = h
         info = PlanInfo()
         _check("ppd_plan_get_info", L.ppd_plan_get_info(h, ctypes.byref(info)))
@@ -193,8 +225,9 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None) is not None:
-            lib().ppd_plan_destroy(self._h)
+            lib().ppd_plan_destroy(self._h)   # synchronises the plan's streams
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:

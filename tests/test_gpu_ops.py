@@ -214,3 +214,48 @@ def test_tile8_item_boundaries(M):
     v = (rng.standard_normal(M) + 1j * rng.standard_normal(M)).astype(np.complex64)
     xg = host(P.ppd_phit(plan, dev(v, torch.complex64), order=P.ORDER_USER))
     assert_op_close(xg, op.phit(v.astype(np.complex128)), what="phit")
+
+
+def test_workspace_plan_matches_allocated_plan():
+    """A plan carved from a PyTorch workspace computes exactly what a plan
+    with library-allocated buffers computes; a too small or misaligned
+    workspace is rejected before any device work."""
+    P = require_gpu()
+    import ctypes
+    import torch
+    announce("workspace plan vs allocated plan")
+    x, wu, wv, off = synth.small_case(64, 5000, seed=21, d=3)
+    pa = P.Plan(64, 64, wu, wv, off, workspace=False)
+    pw = P.Plan(64, 64, wu, wv, off)
+    assert pa.info.device_bytes == pw.info.device_bytes
+    assert pw._ws.numel() >= pw.info.device_bytes
+    assert np.array_equal(pa.permutation(), pw.permutation())
+    x32 = dev(x.astype(np.float32), torch.float32)
+    ya, yw = P.ppd_phi(pa, x32), P.ppd_phi(pw, x32)
+    assert np.array_equal(host(ya), host(yw))
+    assert np.array_equal(host(P.ppd_phit(pa, ya)), host(P.ppd_phit(pw, ya)))
+    eps = 0.5 * np.array([np.linalg.norm(host(ya)[off[j]:off[j + 1]]) for j in range(3)])
+    xs = []
+    for plan in (pa, pw):
+        U = P.ppd_uniform_weights(plan)
+        st = P.PPDState(plan, ya)
+        P.ppd_iterate(plan, st, ya, U, eps, 3, eta=1e-3, mu=1.0)
+        xs.append((host(st.x), host(st.v), host(st.z)))
+    for a, b in zip(*xs):
+        assert np.array_equal(a, b)
+    L = P.lib()
+    wu32, wv32 = np.ascontiguousarray(wu, np.float32), np.ascontiguousarray(wv, np.float32)
+    off64 = np.ascontiguousarray(off, np.int64)
+    desc = P.PlanDesc(64, 64, wu32.size, off64.size - 1, off64.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                      wu32.ctypes.data, wv32.ctypes.data, None, 0.0, 3, 0, 0)
+    need = P.plan_workspace_size(64, 64, wu, wv, off)
+    buf = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    for ptr, size in ((buf.data_ptr(), need - 256), (buf.data_ptr() + 16, need)):
+        h = ctypes.c_void_p()
+        st = L.ppd_plan_create_ws(ctypes.byref(h), ctypes.byref(desc), ctypes.c_void_p(ptr), size,
+                                  ctypes.c_void_p(0))
+        assert st == P.PPD_EINVAL and not h.value
+    h = ctypes.c_void_p()
+    assert L.ppd_plan_create_ws(ctypes.byref(h), ctypes.byref(desc), ctypes.c_void_p(buf.data_ptr()), need,
+                                ctypes.c_void_p(0)) == 0
+    assert L.ppd_plan_destroy(h) == 0

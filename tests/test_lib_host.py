@@ -101,3 +101,22 @@ def test_plan_validation_rejects_before_device_use(P, case):
     with pytest.raises(P.PPDError) as ei:
         P.Plan(stream=_NoStream(), **kw)
     assert ei.value.status in (P.PPD_EINVAL, P.PPD_EUNSUPPORTED)
+
+
+def test_workspace_size_is_a_host_query(P):
+    """The workspace query runs without a device, is reproducible, holds at
+    least the two oversampled grids and grows with the number of points."""
+    rng = np.random.default_rng(1)
+    sizes = []
+    for M in (64, 4096):
+        wu = rng.uniform(-3, 3, M).astype(np.float32)
+        wv = rng.uniform(-3, 3, M).astype(np.float32)
+        off = np.array([0, M // 2, M])
+        a = P.plan_workspace_size(32, 32, wu, wv, off)
+        assert a == P.plan_workspace_size(32, 32, wu, wv, off)
+        assert a % 256 == 0 and a >= 2 * 64 * 64 * 8
+        sizes.append(a)
+    assert sizes[1] > sizes[0]
+    with pytest.raises(P.PPDError) as ei:
+        P.plan_workspace_size(48, 32, wu, wv, off)
+    assert ei.value.status == P.PPD_EUNSUPPORTED
