@@ -891,66 +891,68 @@ __global__ __launch_bounds__(FOLD_CELLS) void k_fold(const float2* __restrict__ 
   grid[size_t(ty * T + a) * Kx + (tx * T + b)] = make_float2(sx, sy);
 }
 
-// 8 x 8 tiles: one tile per workgroup, FOLD8_SPLIT threads per cell (1 by
-// default, measured best with the fold order), thread p taking every
-// FOLD8_SPLIT-th slot from p; the parts are added in a fixed order.
-// Workgroups take the tiles in the plan's fold order: tile rows spread over
-// the XCDs, and on each XCD the tiles with the most item regions first, so
-// the longest sums start first.
-#ifndef PPD_FOLD8_SPLIT
-#define PPD_FOLD8_SPLIT 1
-#endif
-constexpr int FOLD8_SPLIT = PPD_FOLD8_SPLIT;
-
-__device__ __forceinline__ void fold_items_strided(const float2* __restrict__ scratch, int R2, int off, int i0,
-                                                   int i1, float& sx, float& sy) {
-  constexpr int S = FOLD8_SPLIT;
+// 8 x 8 tiles, 4-wave workgroups in the plan's fold order (tile rows spread
+// over the XCDs, on each XCD the tiles with the most item regions first).
+// Entry {t0, t1, t2, t3} folds up to four light tiles, one per wave, one
+// thread per cell; entry {t, -2, -2, -2} folds one heavy tile (more than
+// FOLD_HEAVY regions to sum: the dense centre of the coverage), wave w
+// summing every fourth item region of each source tile from the w-th, the
+// four partial sums then added in wave order.
+__device__ __forceinline__ void fold_items4(const float2* __restrict__ scratch, int R2, int off, int i0, int i1,
+                                            float& sx, float& sy) {
   int i = i0;
-  for (; i + 3 * S < i1; i += 4 * S) {
+  for (; i + 12 < i1; i += 16) {
     const float2 g0 = scratch[size_t(i) * R2 + off];
-    const float2 g1 = scratch[size_t(i + S) * R2 + off];
-    const float2 g2 = scratch[size_t(i + 2 * S) * R2 + off];
-    const float2 g3 = scratch[size_t(i + 3 * S) * R2 + off];
+    const float2 g1 = scratch[size_t(i + 4) * R2 + off];
+    const float2 g2 = scratch[size_t(i + 8) * R2 + off];
+    const float2 g3 = scratch[size_t(i + 12) * R2 + off];
     sx += (g0.x + g1.x) + (g2.x + g3.x);
     sy += (g0.y + g1.y) + (g2.y + g3.y);
   }
-  for (; i < i1; i += S) {
+  for (; i < i1; i += 4) {
     const float2 g = scratch[size_t(i) * R2 + off];
     sx += g.x;
     sy += g.y;
   }
 }
 
-__global__ __launch_bounds__(64 * FOLD8_SPLIT) void k_fold8(const float2* __restrict__ scratch,
-                                                            const int32_t* __restrict__ tio,
-                                                            const int32_t* __restrict__ order, int tiles_x,
-                                                            int tiles_y, int Kx, float2* __restrict__ grid) {
+__global__ __launch_bounds__(256) void k_fold8(const float2* __restrict__ scratch, const int32_t* __restrict__ tio,
+                                                const int4* __restrict__ wgs, int tiles_x, int tiles_y, int Kx,
+                                                float2* __restrict__ grid) {
   constexpr int T = 8, R = T + 7;
-  __shared__ float2 part[FOLD8_SPLIT][64];
-  const int t = order[xcd_remap(blockIdx.x, gridDim.x)];
-  if (t < 0) return;   // padding; uniform over the workgroup
-  const int p = threadIdx.x >> 6, c = threadIdx.x & 63;
+  __shared__ float2 part[4][64];
+  const int4 e = wgs[xcd_remap(blockIdx.x, gridDim.x)];
+  const int w = threadIdx.x >> 6, c = threadIdx.x & 63;
+  const int a = c / T, b = c - a * T;
+  const bool heavy = e.y == -2;   // uniform over the workgroup
+  const int t = heavy ? e.x : (w == 0 ? e.x : w == 1 ? e.y : w == 2 ? e.z : e.w);
+  if (t < 0) return;              // never taken by a heavy workgroup
   const int tx = t % tiles_x, ty = t / tiles_x;
   const int lx = (tx + tiles_x - 1) % tiles_x, uy = (ty + tiles_y - 1) % tiles_y;
   const int tl = ty * tiles_x + lx, tu = uy * tiles_x + tx, tul = uy * tiles_x + lx;
-  const int a = c / T, b = c - a * T;
   float sx = 0.f, sy = 0.f;
-  fold_items_strided(scratch, R * R, a * R + b, tio[t] + p, tio[t + 1], sx, sy);
-  if (b < 7) fold_items_strided(scratch, R * R, a * R + T + b, tio[tl] + p, tio[tl + 1], sx, sy);
-  if (a < 7) {
-    fold_items_strided(scratch, R * R, (T + a) * R + b, tio[tu] + p, tio[tu + 1], sx, sy);
-    if (b < 7) fold_items_strided(scratch, R * R, (T + a) * R + T + b, tio[tul] + p, tio[tul + 1], sx, sy);
-  }
-  part[p][c] = make_float2(sx, sy);
-  __syncthreads();
-  if (p == 0) {
-    float2 s = part[0][c];
-#pragma unroll
-    for (int q = 1; q < FOLD8_SPLIT; ++q) {
-      s.x += part[q][c].x;
-      s.y += part[q][c].y;
+  if (!heavy) {
+    fold_items(scratch, R * R, a * R + b, tio[t], tio[t + 1], sx, sy);
+    if (b < 7) fold_items(scratch, R * R, a * R + T + b, tio[tl], tio[tl + 1], sx, sy);
+    if (a < 7) {
+      fold_items(scratch, R * R, (T + a) * R + b, tio[tu], tio[tu + 1], sx, sy);
+      if (b < 7) fold_items(scratch, R * R, (T + a) * R + T + b, tio[tul], tio[tul + 1], sx, sy);
     }
-    grid[size_t(ty * T + a) * Kx + (tx * T + b)] = s;
+    grid[size_t(ty * T + a) * Kx + (tx * T + b)] = make_float2(sx, sy);
+    return;
+  }
+  fold_items4(scratch, R * R, a * R + b, tio[t] + w, tio[t + 1], sx, sy);
+  if (b < 7) fold_items4(scratch, R * R, a * R + T + b, tio[tl] + w, tio[tl + 1], sx, sy);
+  if (a < 7) {
+    fold_items4(scratch, R * R, (T + a) * R + b, tio[tu] + w, tio[tu + 1], sx, sy);
+    if (b < 7) fold_items4(scratch, R * R, (T + a) * R + T + b, tio[tul] + w, tio[tul + 1], sx, sy);
+  }
+  part[w][c] = make_float2(sx, sy);
+  __syncthreads();
+  if (w == 0) {
+    const float2 p0 = part[0][c], p1 = part[1][c], p2 = part[2][c], p3 = part[3][c];
+    grid[size_t(ty * T + a) * Kx + (tx * T + b)] =
+        make_float2(((p0.x + p1.x) + p2.x) + p3.x, ((p0.y + p1.y) + p2.y) + p3.y);
   }
 }
 
@@ -1048,8 +1050,8 @@ int launch_fold(ppd_plan* p) {
 }
 
 int launch_fold8(ppd_plan* p) {
-  hipLaunchKernelGGL(k_fold8, dim3(p->n_fold_launch), dim3(64 * FOLD8_SPLIT), 0, p->stream, p->gscratch,
-                     p->tile_item_off, p->fold_order, p->tiles_x, p->tiles_y, p->Kx, p->grid_a);
+  hipLaunchKernelGGL(k_fold8, dim3(p->n_fold_wg), dim3(256), 0, p->stream, p->gscratch, p->tile_item_off,
+                     reinterpret_cast<const int4*>(p->fold_wg), p->tiles_x, p->tiles_y, p->Kx, p->grid_a);
   PPD_HIP(hipGetLastError());
   return PPD_OK;
 }

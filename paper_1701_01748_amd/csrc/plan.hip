@@ -394,9 +394,11 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   // neighbours, which share cache lines of the item regions, meet in one L2;
   // the dense rows are spread over all XCDs), and each XCD takes its tiles
   // by decreasing number of item regions to sum (own and left / upper /
-  // upper-left halos), so the long sums start first.  Lists are padded to a
-  // common length with -1 (no tile).
-  std::vector<int32_t> fold_order;
+  // upper-left halos), so the long sums start first.  The per-XCD lists of
+  // fold workgroups (4 tile slots each) are padded to a common length with
+  // -1 (no tile).
+  std::vector<int32_t> fold_wg;
+  std::vector<std::vector<int32_t>> fold_wg_lists;
   {
     std::vector<int32_t> work(ntiles);
     for (int t = 0; t < ntiles; ++t) {
@@ -407,14 +409,30 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
     }
     std::vector<std::vector<int32_t>> lists(MAX_XCD);
     for (int t = 0; t < ntiles; ++t) lists[(t / p->tiles_x) % MAX_XCD].push_back(t);
-    size_t per = 0;
-    for (auto& l : lists) {
+    for (auto& l : lists)
       std::stable_sort(l.begin(), l.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
-      per = std::max(per, l.size());
-    }
     for (auto& l : lists) {
-      l.resize(per, -1);
-      fold_order.insert(fold_order.end(), l.begin(), l.end());
+      // workgroups of the 4-wave fold: a tile with more than FOLD_HEAVY item
+      // regions to sum gets all four waves, the others go four to a
+      // workgroup, in the same per-XCD order
+      std::vector<int32_t> wg;
+      for (size_t i = 0; i < l.size();) {
+        if (work[l[i]] > FOLD_HEAVY) {
+          wg.insert(wg.end(), {l[i], -2, -2, -2});
+          ++i;
+          continue;
+        }
+        int32_t e[4] = {-1, -1, -1, -1};
+        for (int k = 0; k < 4 && i < l.size() && work[l[i]] <= FOLD_HEAVY; ++k) e[k] = l[i++];
+        wg.insert(wg.end(), e, e + 4);
+      }
+      fold_wg_lists.push_back(wg);
+    }
+    size_t per_wg = 0;
+    for (auto& w : fold_wg_lists) per_wg = std::max(per_wg, w.size());
+    for (auto& w : fold_wg_lists) {
+      w.resize(per_wg, -1);
+      fold_wg.insert(fold_wg.end(), w.begin(), w.end());
     }
   }
   p->n_items = int(items.size());
@@ -496,8 +514,8 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   A(dalloc(p, &p->items, p->n_items));
   A(dalloc(p, &p->segs, p->n_segs));
   A(dalloc(p, &p->tile_item_off, ntiles + 1));
-  A(dalloc(p, &p->fold_order, fold_order.size()));
-  p->n_fold_launch = int(fold_order.size());
+  A(dalloc(p, &p->fold_wg, fold_wg.size()));
+  p->n_fold_wg = int(fold_wg.size() / 4);
   A(dalloc(p, &p->bseg_ids, p->n_segs));
   A(dalloc(p, &p->bseg_off_d, p->d + 1));
   A(dalloc(p, &p->bfac, p->d));
@@ -562,7 +580,7 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   up(p->items, items.data(), sizeof(Item) * p->n_items);
   up(p->segs, segs.data(), sizeof(Seg) * p->n_segs);
   up(p->tile_item_off, tile_item_off.data(), 4 * (ntiles + 1));
-  up(p->fold_order, fold_order.data(), 4 * fold_order.size());
+  up(p->fold_wg, fold_wg.data(), 4 * fold_wg.size());
   up(p->sec_cstart, cstart.data(), 4 * cstart.size());
   up(p->sec_cblock, cblock.data(), 4 * cblock.size());
   up(p->sec_coff, coff.data(), 4 * coff.size());

@@ -37,6 +37,10 @@ constexpr int FILT_STRIDE = 16;   // max Daubechies taps (db8)
 constexpr int SEC_CHUNK = 2048;   // points per workgroup of an exact-prox Newton pass
 constexpr int MAX_ITEM_SEGS = 64; // per-block segments of one work item (one wave scans them)
 constexpr int MAX_XCD = 8;
+#ifndef PPD_FOLD_HEAVY
+#define PPD_FOLD_HEAVY 16
+#endif
+constexpr int FOLD_HEAVY = PPD_FOLD_HEAVY;   // item regions above which a tile's fold takes a whole workgroup
 
 // A segment: plan-order visibilities [start, start+count) of one data
 // block whose first tap lies in one grid tile.
@@ -95,8 +99,8 @@ struct ppd_plan {
   ppd::Item* items = nullptr;
   ppd::Seg* segs = nullptr;
   int32_t* tile_item_off = nullptr;        // [n_tiles+1] items of each tile
-  int32_t* fold_order = nullptr;           // [n_fold_launch] tile per fold workgroup (-1: none)
-  int n_fold_launch = 0;                   // multiple of MAX_XCD
+  int32_t* fold_wg = nullptr;              // [n_fold_wg][4] tiles per 4-wave fold workgroup
+  int n_fold_wg = 0;                       // multiple of MAX_XCD
   int32_t* bseg_ids = nullptr;             // segment ids grouped by block
   int32_t* bseg_off_d = nullptr;           // [d+1]
   float2* gscratch = nullptr;              // [n_items][(T+7)^2] gridding partials

@@ -185,14 +185,15 @@ def test_operator_norm_matches_oracle():
     assert abs(g - ref) / ref < 1e-5, (g, ref, it)
 
 
-@pytest.mark.parametrize("M", [1, 63, 64, 65, 127, 128, 129, 300])
+@pytest.mark.parametrize("M", [1, 63, 64, 65, 127, 128, 129, 300, 4000])
 def test_tile8_item_boundaries(M):
     """All points in one 8 x 8 tile whose halo wraps around the grid edge
     (first taps in the last tile row and column), so that one tile's item
     split (128-point pieces plus a remainder), the batch tails (64-point
     batches), the run pipeline of the matrix-core gridding and the fold's
     wrapped halos are exercised at their boundaries; two blocks share the
-    tile when M > 1."""
+    tile when M > 1.  With 4000 points the tile holds 32 items: its fold and
+    its neighbours' take a whole workgroup each (heavy tiles)."""
     P = require_gpu()
     import torch
     announce(f"tile-8 boundaries M={M}")
