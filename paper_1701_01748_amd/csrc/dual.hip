@@ -96,19 +96,23 @@ __global__ __launch_bounds__(64 * ALG2_WAVES) void k_alg2(
 // workgroup j sums the segment partials of ||q - y_j||^2 in a fixed order
 // and stores (eps_j / r, 0) if r > eps_j, else (1, 1).
 constexpr int BF_PER = 8;
-__global__ __launch_bounds__(256) void k_block_factors(const double* __restrict__ part,
-                                                       const int32_t* __restrict__ bids,
-                                                       const int32_t* __restrict__ boff,
-                                                       const double* __restrict__ eps, double2* __restrict__ bfac) {
-  __shared__ double red[4];
+// One pass of 1024 threads covers up to 8192 segments (the largest block of
+// the 512^2, 1.3M workload has ~3k); 256 threads took two passes there.
+constexpr int BF_THREADS = 1024;
+__global__ __launch_bounds__(BF_THREADS) void k_block_factors(const double* __restrict__ part,
+                                                              const int32_t* __restrict__ bids,
+                                                              const int32_t* __restrict__ boff,
+                                                              const double* __restrict__ eps,
+                                                              double2* __restrict__ bfac) {
+  __shared__ double red[BF_THREADS / 64];
   const int j = blockIdx.x;
   const int c0 = boff[j], c1 = boff[j + 1];
   double s = 0.0;
-  for (int base = c0; base < c1; base += 256 * BF_PER) {
+  for (int base = c0; base < c1; base += BF_THREADS * BF_PER) {
     int id[BF_PER];
 #pragma unroll
     for (int k = 0; k < BF_PER; ++k) {
-      const int c = base + int(threadIdx.x) + k * 256;
+      const int c = base + int(threadIdx.x) + k * BF_THREADS;
       id[k] = c < c1 ? bids[c] : -1;
     }
     double v[BF_PER];
@@ -121,7 +125,9 @@ __global__ __launch_bounds__(256) void k_block_factors(const double* __restrict_
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double r = sqrt((red[0] + red[1]) + (red[2] + red[3])), e = eps[j];
+    double t = 0.0;
+    for (int q = 0; q < BF_THREADS / 64; ++q) t += red[q];
+    const double r = sqrt(t), e = eps[j];
     bfac[j] = r > e ? make_double2(e / r, 0.0) : make_double2(1.0, 1.0);
   }
 }
@@ -404,7 +410,7 @@ int secular_solve(ppd_plan* p, const double2* w, const float2* v, const float2* 
 int block_factors(ppd_plan* p, const double* part) {
   int slot;
   PPD_TRY(timer_begin(p, KK_MISC, &slot));
-  hipLaunchKernelGGL(k_block_factors, dim3(p->d), dim3(256), 0, p->stream, part, p->bseg_ids, p->bseg_off_d,
+  hipLaunchKernelGGL(k_block_factors, dim3(p->d), dim3(BF_THREADS), 0, p->stream, part, p->bseg_ids, p->bseg_off_d,
                      p->eps_d, p->bfac);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
