@@ -25,14 +25,16 @@ __device__ inline double block_sum(double v, double* red) {
 //   mode 0: partials of ||q - y||^2, q = z - mu U (z - w)   (z unchanged)
 //   mode 1: z <- P_B(q) with the block factors, then partials of the next q
 //   mode 2: z <- P_B(q) only
-constexpr int ALG2_WAVES = 4;
-__global__ __launch_bounds__(64 * ALG2_WAVES) void k_alg2(
+// NW waves per workgroup: 1 for items of at most two batches (the 8 x 8
+// default, 128 points: 4 waves left half of them idle, 296 against 242 us
+// per iteration with n_itr = 5 at 512^2, 1.3M), else 4.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_alg2(
     int mode, const Item* __restrict__ items, int n_items, const Seg* __restrict__ segs,
     const double2* __restrict__ w, const float2* __restrict__ v, const float2* __restrict__ ga,
     const float2* __restrict__ y, const double* __restrict__ U,
     double2* __restrict__ z, double mu, const double2* __restrict__ bfac, const uint8_t* __restrict__ active,
     double* __restrict__ part_out) {
-  constexpr int NW = ALG2_WAVES;
   __shared__ ItemTab tab;
   __shared__ double s_q[NW][MAX_ITEM_SEGS];
   const int ii = xcd_remap(blockIdx.x, gridDim.x);
@@ -377,8 +379,12 @@ int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* v, const 
   if (mode != 0) PPD_TRY(block_factors(p, part_in));
   int slot;
   PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
-  hipLaunchKernelGGL(k_alg2, dim3(p->n_launch), dim3(64 * ALG2_WAVES), 0, p->stream, mode, p->items, p->n_items,
-                     p->segs, w, v, ga, y, U, z, mu, p->bfac, active, part_out);
+  if (p->chunk_max <= 128)
+    hipLaunchKernelGGL(k_alg2<1>, dim3(p->n_launch), dim3(64), 0, p->stream, mode, p->items, p->n_items,
+                       p->segs, w, v, ga, y, U, z, mu, p->bfac, active, part_out);
+  else
+    hipLaunchKernelGGL(k_alg2<4>, dim3(p->n_launch), dim3(256), 0, p->stream, mode, p->items, p->n_items,
+                       p->segs, w, v, ga, y, U, z, mu, p->bfac, active, part_out);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }
