@@ -145,19 +145,68 @@ __global__ __launch_bounds__(BF_THREADS) void k_block_factors(const double* __re
 // one block (blocks are contiguous in plan order).  The first pass forms
 // a^2 = U^2 |w - y|^2 and keeps (a^2, U) per point, the later ones read only
 // that (16 bytes per point); each workgroup writes its chunk's S2, S3 at the
-// block's current nu, summed in a fixed order (deterministic).
+// block's current nu, summed in a fixed order (deterministic).  A later
+// pass first takes the Newton step from the previous pass's partials
+// itself (every workgroup of a block computes the same value in the same
+// order), so one launch per step remains; partials and nu alternate
+// between two buffers, and a last k_sec_update takes the final step.
 constexpr int SEC_THREADS = 256;
 
+// Newton step of block j from its chunk partials [c0, c1): nu = max(0, nu0
+// - g / g'), g = 1 / r - 1 / eps.  All SEC_THREADS threads take part; the
+// result is returned to every thread.
+__device__ double newton_nu(const double* __restrict__ p2, const double* __restrict__ p3, int c0, int c1,
+                            double eps, double nu0, double* red2, double* red3, double* out) {
+  double a = 0.0, b = 0.0;
+  for (int c = c0 + int(threadIdx.x); c < c1; c += SEC_THREADS) {
+    a += p2[c];
+    b += p3[c];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    red2[threadIdx.x >> 6] = a;
+    red3[threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S2 = 0.0, S3 = 0.0;
+#pragma unroll
+    for (int k = 0; k < SEC_THREADS / 64; ++k) {
+      S2 += red2[k];
+      S3 += red3[k];
+    }
+    double nu = 0.0;
+    if (S2 > 0.0 && S3 > 0.0) {
+      const double r = sqrt(S2);
+      const double g = 1.0 / r - 1.0 / eps, gp = S3 / (r * r * r);
+      nu = fmax(0.0, nu0 - g / gp);
+    }
+    *out = nu;
+  }
+  __syncthreads();
+  return *out;
+}
+
+// FIRST: nu = 0.  Else the step from the previous partials (pp2, pp3) and
+// the previous nu (pnu, NULL after the first pass); the chunk that starts
+// its block stores the new nu to nnu.
 template <bool FIRST>
 __global__ __launch_bounds__(SEC_THREADS) void k_sec_chunk(
-    const int32_t* __restrict__ cstart, const int32_t* __restrict__ cblock, const double2* __restrict__ w,
-    const float2* __restrict__ v, const float2* __restrict__ ga, const float2* __restrict__ y,
-    const double* __restrict__ U, const double2* __restrict__ bfac, double2* __restrict__ aq,
-    double* __restrict__ p2, double* __restrict__ p3) {
-  __shared__ double red2[SEC_THREADS / 64], red3[SEC_THREADS / 64];
+    const int32_t* __restrict__ cstart, const int32_t* __restrict__ cblock, const int32_t* __restrict__ coff,
+    const double* __restrict__ eps, const double2* __restrict__ w, const float2* __restrict__ v,
+    const float2* __restrict__ ga, const float2* __restrict__ y, const double* __restrict__ U,
+    double2* __restrict__ aq, const double* __restrict__ pp2, const double* __restrict__ pp3,
+    const double* __restrict__ pnu, double* __restrict__ nnu, double* __restrict__ p2, double* __restrict__ p3) {
+  __shared__ double red2[SEC_THREADS / 64], red3[SEC_THREADS / 64], s_nu;
   const int c = blockIdx.x;
   const int i0 = cstart[c], i1 = cstart[c + 1];
-  const double nu = FIRST ? 0.0 : bfac[cblock[c]].x;
+  double nu = 0.0;
+  if (!FIRST) {
+    const int j = cblock[c];
+    nu = newton_nu(pp2, pp3, coff[j], coff[j + 1], eps[j], pnu ? pnu[j] : 0.0, red2, red3, &s_nu);
+    if (c == coff[j] && threadIdx.x == 0) nnu[j] = nu;
+  }
   double t2 = 0.0, t3 = 0.0;
 #pragma unroll 4
   for (int i = i0 + int(threadIdx.x); i < i1; i += SEC_THREADS) {
@@ -181,6 +230,7 @@ __global__ __launch_bounds__(SEC_THREADS) void k_sec_chunk(
   }
   t2 = wave_sum(t2);
   t3 = wave_sum(t3);
+  __syncthreads();   // red2 / red3 reused after newton_nu
   if ((threadIdx.x & 63) == 0) {
     red2[threadIdx.x >> 6] = t2;
     red3[threadIdx.x >> 6] = t3;
@@ -198,39 +248,18 @@ __global__ __launch_bounds__(SEC_THREADS) void k_sec_chunk(
   }
 }
 
-// One Newton step per block: workgroup j sums its chunks' partials in a
-// fixed order and updates nu_j = max(0, nu_j - g / g').
-__global__ __launch_bounds__(256) void k_sec_update(const double* __restrict__ p2, const double* __restrict__ p3,
-                                                    const int32_t* __restrict__ coff,
-                                                    const double* __restrict__ eps, int first,
-                                                    double2* __restrict__ bfac) {
-  __shared__ double red2[4], red3[4];
+// The last Newton step: workgroup j takes it from the last pass's partials
+// and stores nu_j to the block factors.
+__global__ __launch_bounds__(SEC_THREADS) void k_sec_update(const double* __restrict__ p2,
+                                                            const double* __restrict__ p3,
+                                                            const int32_t* __restrict__ coff,
+                                                            const double* __restrict__ eps,
+                                                            const double* __restrict__ pnu,
+                                                            double2* __restrict__ bfac) {
+  __shared__ double red2[SEC_THREADS / 64], red3[SEC_THREADS / 64], s_nu;
   const int j = blockIdx.x;
-  const int c0 = coff[j], c1 = coff[j + 1];
-  double a = 0.0, b = 0.0;
-  for (int c = c0 + int(threadIdx.x); c < c1; c += 256) {
-    a += p2[c];
-    b += p3[c];
-  }
-  a = wave_sum(a);
-  b = wave_sum(b);
-  if ((threadIdx.x & 63) == 0) {
-    red2[threadIdx.x >> 6] = a;
-    red3[threadIdx.x >> 6] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double S2 = (red2[0] + red2[1]) + (red2[2] + red2[3]);
-    const double S3 = (red3[0] + red3[1]) + (red3[2] + red3[3]);
-    const double nu0 = first ? 0.0 : bfac[j].x;
-    double nu = 0.0;
-    if (S2 > 0.0 && S3 > 0.0) {
-      const double r = sqrt(S2), e = eps[j];
-      const double g = 1.0 / r - 1.0 / e, gp = S3 / (r * r * r);
-      nu = fmax(0.0, nu0 - g / gp);
-    }
-    bfac[j] = make_double2(nu, 0.0);
-  }
+  const double nu = newton_nu(p2, p3, coff[j], coff[j + 1], eps[j], pnu ? pnu[j] : 0.0, red2, red3, &s_nu);
+  if (threadIdx.x == 0) bfac[j] = make_double2(nu, 0.0);
 }
 
 // z = (U w + nu y) / (U + nu) with the block's nu (z = w when nu = 0).
@@ -391,26 +420,36 @@ int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* v, const 
 
 int secular_solve(ppd_plan* p, const double2* w, const float2* v, const float2* ga, const float2* y,
                   const double* U, int n_newton) {
-  double* p2 = p->sec_part;
-  double* p3 = p->sec_part + p->n_sec_chunks;
+  // pass s writes its partials to buffer s & 1 and (s >= 1) its nu to
+  // nu buffer s & 1
+  const int nc = p->n_sec_chunks;
+  double* part[2] = {p->sec_part, p->sec_part + 2 * nc};
+  double* nub[2] = {p->sec_nu, p->sec_nu + p->d};
   for (int s = 0; s < n_newton; ++s) {
+    double* p2 = part[s & 1];
+    double* p3 = part[s & 1] + nc;
+    const double* q2 = part[(s + 1) & 1];
+    const double* q3 = part[(s + 1) & 1] + nc;
+    const double* pnu = s >= 2 ? nub[(s + 1) & 1] : nullptr;
     int slot;
     PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
     if (s == 0)
-      hipLaunchKernelGGL(k_sec_chunk<true>, dim3(p->n_sec_chunks), dim3(SEC_THREADS), 0, p->stream, p->sec_cstart,
-                         p->sec_cblock, w, v, ga, y, U, p->bfac, p->qbuf, p2, p3);
+      hipLaunchKernelGGL(k_sec_chunk<true>, dim3(nc), dim3(SEC_THREADS), 0, p->stream, p->sec_cstart, p->sec_cblock,
+                         p->sec_coff, p->eps_d, w, v, ga, y, U, p->qbuf, nullptr, nullptr, nullptr, nullptr, p2, p3);
     else
-      hipLaunchKernelGGL(k_sec_chunk<false>, dim3(p->n_sec_chunks), dim3(SEC_THREADS), 0, p->stream, p->sec_cstart,
-                         p->sec_cblock, w, v, ga, y, U, p->bfac, p->qbuf, p2, p3);
-    PPD_HIP(hipGetLastError());
-    PPD_TRY(timer_end(p, slot));
-    PPD_TRY(timer_begin(p, KK_MISC, &slot));
-    hipLaunchKernelGGL(k_sec_update, dim3(p->d), dim3(256), 0, p->stream, p2, p3, p->sec_coff, p->eps_d,
-                       int(s == 0), p->bfac);
+      hipLaunchKernelGGL(k_sec_chunk<false>, dim3(nc), dim3(SEC_THREADS), 0, p->stream, p->sec_cstart,
+                         p->sec_cblock, p->sec_coff, p->eps_d, w, v, ga, y, U, p->qbuf, q2, q3, pnu, nub[s & 1], p2,
+                         p3);
     PPD_HIP(hipGetLastError());
     PPD_TRY(timer_end(p, slot));
   }
-  return PPD_OK;
+  const int last = n_newton - 1;
+  int slot;
+  PPD_TRY(timer_begin(p, KK_MISC, &slot));
+  hipLaunchKernelGGL(k_sec_update, dim3(p->d), dim3(SEC_THREADS), 0, p->stream, part[last & 1],
+                     part[last & 1] + nc, p->sec_coff, p->eps_d, last >= 1 ? nub[last & 1] : nullptr, p->bfac);
+  PPD_HIP(hipGetLastError());
+  return timer_end(p, slot);
 }
 
 int block_factors(ppd_plan* p, const double* part) {

@@ -538,7 +538,8 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   A(dalloc(p, &p->sec_cstart, cstart.size()));
   A(dalloc(p, &p->sec_cblock, cblock.size()));
   A(dalloc(p, &p->sec_coff, coff.size()));
-  A(dalloc(p, &p->sec_part, 2 * cblock.size()));
+  A(dalloc(p, &p->sec_part, 4 * cblock.size()));
+  A(dalloc(p, &p->sec_nu, 2 * size_t(p->d)));
   A(dalloc(p, &p->part, 2 * size_t(p->n_segs)));
   A(dalloc(p, &p->rpart, p->n_segs));
   A(dalloc(p, &p->eps_d, p->d));

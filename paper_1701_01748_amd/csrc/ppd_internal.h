@@ -127,7 +127,8 @@ struct ppd_plan {
   int32_t* sec_cstart = nullptr;           // [n_sec_chunks + 1] first visibility of each chunk
   int32_t* sec_cblock = nullptr;           // [n_sec_chunks] block of each chunk
   int32_t* sec_coff = nullptr;             // [d + 1] chunks of block j: [sec_coff[j], sec_coff[j+1])
-  double* sec_part = nullptr;              // [2][n_sec_chunks] S2, S3 partials
+  double* sec_part = nullptr;              // [2][2][n_sec_chunks] S2, S3 partials, two passes
+  double* sec_nu = nullptr;                // [2][d] nu of the last two Newton passes
   double* part = nullptr;                  // [2][n_segs] block-norm partials
   double* rpart = nullptr;                 // [n_segs] residual partials
   double* eps_d = nullptr;                 // [d]
