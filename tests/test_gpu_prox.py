@@ -133,3 +133,50 @@ def test_subiterations_vs_exact_tracks256():
     assert abs(curves["fb50"][-1] - curves["exact"][-1]) < 0.1
     for name in ("fb1", "fb5", "fb50", "exact"):
         assert curves[name][-1] > curves["pd"][-1]
+
+
+def test_newton_steps_follow_the_secular_iteration():
+    """nu after 1, 2, 3 and 5 Newton steps (each pass takes the previous
+    step, one last launch the final one, with the passes' partials and nu
+    alternating between two buffers) equals the same Newton sequence on the
+    secular equation run in FP64 on the host, and climbs monotonically
+    toward the oracle's multiplier (recovered from its exact prox)."""
+    P = require_gpu()
+    import torch
+    announce("prox metric Newton steps 1, 2, 3, 5")
+    n, M = 64, 20000
+    x, wu, wv, off = synth.small_case(n, M, seed=47, d=4)
+    plan = P.Plan(n, n, wu, wv, off)
+    perm = plan.permutation()
+    rng = np.random.default_rng(13)
+    y = (rng.standard_normal(M) + 1j * rng.standard_normal(M)).astype(np.complex64)
+    w = y.astype(np.complex128) + 0.3 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    U = np.exp(rng.uniform(np.log(1e-3), 0.0, M))
+    eps = np.array([0.5, 0.9, 2.0, 0.1]) * np.array(
+        [np.linalg.norm(w[off[j]:off[j + 1]] - y[off[j]:off[j + 1]]) for j in range(4)])
+    # the multiplier of the exact prox, from the oracle's z: z - y = U (w - y) / (U + nu)
+    nu_exact = np.zeros(4)
+    for j in (0, 1, 3):
+        s = slice(off[j], off[j + 1])
+        z = oprox.prox_metric_exact(w[s], y[s].astype(np.complex128), eps[j], U[s])
+        nu_exact[j] = float(np.median(U[s] * np.abs(w[s] - y[s]) / np.abs(z - y[s]) - U[s]))
+    prev = np.zeros(4)
+    for k in (1, 2, 3, 5):
+        nu = dev(np.zeros(4), torch.float64)
+        P.ppd_prox_metric(plan, dev(w[perm], torch.complex128), dev(y[perm], torch.complex64),
+                          dev(U[perm], torch.float64), eps, n_newton=k, nu=nu)
+        got = host(nu)
+        for j in range(4):
+            s = slice(off[j], off[j + 1])
+            a2 = U[s] ** 2 * np.abs(w[s] - y[s].astype(np.complex128)) ** 2
+            v = 0.0
+            for _ in range(k):
+                S2 = np.sum(a2 / (U[s] + v) ** 2)
+                S3 = np.sum(a2 / (U[s] + v) ** 3)
+                r = np.sqrt(S2)
+                v = max(0.0, v - (1.0 / r - 1.0 / eps[j]) / (S3 / r ** 3))
+            assert abs(got[j] - v) <= 1e-10 * max(v, 1e-300) + 1e-300, (k, j, got[j], v)
+            assert got[j] >= prev[j] * (1 - 1e-12) and got[j] <= nu_exact[j] * (1 + 1e-9) + 1e-300, (k, j)
+        assert got[2] == 0.0   # inside the ball
+        prev = got
+    assert np.all(np.abs(prev[[0, 1, 3]] - nu_exact[[0, 1, 3]]) <= 1e-6 * nu_exact[[0, 1, 3]])
