@@ -283,14 +283,14 @@ __global__ void k_fft_rows_inv(const float2* __restrict__ half, const float2* __
       const double dn = double(xnf) - xo;
       dx2 += dn * dn;
       xx += double(xnf) * double(xnf);
-      if (x_true) {
+      if (part && x_true) {
         const double tv = x_true[idx];
         ee += (tv - double(xnf)) * (tv - double(xnf));
         tt += tv * tv;
       }
     }
   }
-  if (PRIMAL) {
+  if (PRIMAL && part) {   // statistics partials only when the call reads them (uniform branch)
     dx2 = block_sum(dx2, red);
     xx = block_sum(xx, red);
     ee = block_sum(ee, red);

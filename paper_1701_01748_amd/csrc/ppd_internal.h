@@ -182,7 +182,7 @@ int fft_cols_inverse(ppd_plan* p);                             // grid_a -> half
 struct PrimalArgs {
   float* x; float* xt; const float* ut; const float* x_true;
   double tau, eta, zeta, lambda;
-  double* part;                                                // [ny][4]
+  double* part;                    // [ny][4] statistics partials, or NULL to skip them
 };
 // half -> primal update; with next != NULL also the forward row pass of the
 // new x~ into next (ny x Kx)
