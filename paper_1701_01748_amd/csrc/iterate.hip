@@ -199,10 +199,11 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
 
 std::string graph_key(const IterCtx& c) {
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d %d %d",
+  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d %d %d",
                 (void*)c.dual.y, (void*)c.dual.U, (void*)c.dual.v, (void*)c.dual.z, (void*)c.primal.x,
                 (void*)c.primal.xt, (void*)c.primal.x_true, (void*)c.u, (void*)c.primal.ut, (void*)c.W,
-                (const void*)c.dual.active, (const void*)c.basis_active, (const void*)c.primal.part, c.dual.mu,
+                (const void*)c.dual.active, (const void*)c.basis_active, (const void*)c.primal.part, (const void*)c.dual.rpart,
+                c.dual.mu,
                 c.dual.lambda, c.primal.tau, c.primal.eta, c.primal.zeta, double(c.alpha),
                 double(c.lambda), c.dual.n_itr, c.form, c.prox, c.n_newton);
   return std::string(buf);
@@ -268,6 +269,7 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   c.primal.lambda = prm->lambda;
   // statistics partials of the new iterate only when this call reports them
   c.primal.part = (stats || residual) ? p->ppart : nullptr;
+  c.dual.rpart = (stats || residual) ? p->rpart : nullptr;
   c.u = st->u;
   c.W = prm->W;
   c.alpha = float(prm->alpha);
@@ -308,7 +310,10 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
     } else {
       for (int t = 0; t < n_iter; ++t) {
         IterCtx ct = c;
-        if (t + 1 < n_iter) ct.primal.part = nullptr;   // only the last iteration's are read
+        if (t + 1 < n_iter) {   // only the last iteration's statistics partials are read
+          ct.primal.part = nullptr;
+          ct.dual.rpart = nullptr;
+        }
         PPD_TRY(one_iteration(p, ct));
       }
     }

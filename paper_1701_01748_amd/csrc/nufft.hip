@@ -265,7 +265,7 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
       const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
       for (int ss = sb; ss <= slast; ++ss) {
         const double a = wave_sum(act && sg == ss ? qn : 0.0);
-        const double r = wave_sum(act && sg == ss ? rn : 0.0);
+        const double r = rpart ? wave_sum(act && sg == ss ? rn : 0.0) : 0.0;
         if (lane == 0) {
           s_q[uwid][ss] += a;
           s_r[uwid][ss] += r;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
         r += s_r[w][k];
       }
       part[it.seg0 + k] = q;
-      rpart[it.seg0 + k] = r;
+      if (rpart) rpart[it.seg0 + k] = r;
     }
   }
 }
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(64) void k_degrid8(
       const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
       for (int ss = sb; ss <= slast; ++ss) {
         const double a = wave_sum(act && sg == ss ? qn : 0.0);
-        const double r = wave_sum(act && sg == ss ? rn : 0.0);
+        const double r = rpart ? wave_sum(act && sg == ss ? rn : 0.0) : 0.0;   // statistics only
         if (lane == ss) {
           q_acc += a;
           r_acc += r;
@@ -698,7 +698,7 @@ __global__ __launch_bounds__(64) void k_degrid8(
     }
     if (lane < nseg) {
       part[seg0 + lane] = q_acc;
-      rpart[seg0 + lane] = r_acc;
+      if (rpart) rpart[seg0 + lane] = r_acc;
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -979,7 +979,7 @@ int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double
   if (T == 8 && PPD_DEGRID_RUN > 0 && dual) {
     hipLaunchKernelGGL(k_degrid8, dim3(degrid8_launch(p)), dim3(64), 0, p->stream, p->grid_f, p->Kx, p->Ky,
                        p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale, p->sv_scale, p->kbc,
-                       a->y, a->U, a->v, a->z, p->gabuf, a->mu, part_out, p->rpart);
+                       a->y, a->U, a->v, a->z, p->gabuf, a->mu, part_out, a->rpart);
     PPD_HIP(hipGetLastError());
     return PPD_OK;
   }
@@ -992,7 +992,7 @@ int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double
     hipLaunchKernelGGL((k_degrid<T, true>), dim3(p->n_launch), dim3(64 * DegridCfg<T>::NW), 0, p->stream, p->grid_f,
                        p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->gabuf, a->mu,
-                       part_out, p->rpart);
+                       part_out, a->rpart);
   }
   PPD_HIP(hipGetLastError());
   return PPD_OK;

@@ -195,6 +195,7 @@ struct DualArgs {
   double mu, lambda;
   int n_itr;
   const uint8_t* active;   // DEVICE [d] block mask of this iteration, NULL = all
+  double* rpart = nullptr; // DEVICE [n_segs] residual partials for the statistics, NULL = skip them
 };
 int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out);   // grid_f -> gabuf
 int grid_plain(ppd_plan* p, const float2* v);                 // v -> grid_a (accumulate)
