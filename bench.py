@@ -7,7 +7,10 @@ radial coverage in 16 uneven blocks (20k..200k), 30 dB input SNR, SARA with
 Algorithm 3 (forward FFT, degridding with the fused dual update, gridding,
 inverse FFT, SARA analysis + dual clip + synthesis, primal update), replayed
 from a captured HIP graph or launched eagerly on two streams (both timed,
-the faster is the value), inputs resident in HBM.
+the faster is the value), inputs resident in HBM; the statistics (relative
+change, SNR, block residuals) of every --stats-every-th (10th) iteration
+are reduced on the device during the timed call, as a stopping test would,
+and the call ends by reading back the last ones.
 
 Prints one JSON line: PPD iterations/s (value), Phi / Phi^H visibilities/s,
 the plain (unfused, per-block FP64) form for comparison, the roofline of the
@@ -100,6 +103,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ppd512")
     ap.add_argument("--n-itr", type=int, default=1)
+    ap.add_argument("--stats-every", type=int, default=10,
+                    help="the statistics (relative change, SNR, block residuals) of every this-many-th "
+                         "iteration are reduced on the device during the timed call, as a stopping test")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements (profiling runs)")
@@ -168,15 +174,26 @@ def main():
 
     # ---- timed region: the fused iteration, replayed from a HIP graph and
     # launched eagerly (two streams); the faster of the two is the value ----
+    # The statistics (step a12: relative change, SNR, block residuals over
+    # eps) are part of the step: those of every `stats_every`-th iteration are
+    # reduced on the device during the call into a history, as a stopping
+    # test would, and the call ends by reading back the last ones.
+    every = max(1, args.stats_every)
+    hist = torch.zeros((args.steps // every) * (8 + len(off) - 1), dtype=torch.float64, device="cuda")
+
     def timed(graph: bool):
-        P.ppd_iterate(plan, state, y, U, eps, args.warmup, use_graph=graph, stats=False, **kw)
+        P.ppd_iterate(plan, state, y, U, eps, args.warmup, use_graph=graph, x_true=x_true, stats_every=every,
+                      **kw)   # also captures the graph
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(stream)
-        P.ppd_iterate(plan, state, y, U, eps, args.steps, use_graph=graph, stats=False, **kw)
+        st = P.ppd_iterate(plan, state, y, U, eps, args.steps, use_graph=graph, x_true=x_true, stats_every=every,
+                           stats_history=hist, **kw)
         e1.record(stream)
         torch.cuda.synchronize()
+        h = hist.view(-1, 8 + len(off) - 1).cpu().numpy()
+        assert np.isfinite(st["rel_change"]) and np.all(np.isfinite(h[:, :2]))
         return time.perf_counter() - t0, e0.elapsed_time(e1)
 
     wall_g, ev_g = timed(True)
@@ -195,6 +212,7 @@ def main():
                    "n_itr": args.n_itr, "levels": 3,
                    "form": "fused, hip graph" if use_graph else "fused, eager two-stream", "tile": info.tile,
                    "chunk": info.chunk},
+        "stats_every": every,
         "event_ms_per_step": round(ev_ms / args.steps, 4),
         "graph_iters_per_s": round(args.steps / wall_g, 2), "eager_iters_per_s": round(args.steps / wall_e, 2),
         "snr_db_after": round(st["snr_db"], 3), "iterations_done": st["iter"],
@@ -206,7 +224,7 @@ def main():
     n_prof = 10
     plan.timing(True)
     plan.timing_reset()
-    P.ppd_iterate(plan, state, y, U, eps, n_prof, use_graph=False, stats=False, **kw)
+    P.ppd_iterate(plan, state, y, U, eps, n_prof, use_graph=False, x_true=x_true, **kw)
     tk = plan.timing_read()
     plan.timing(False)
     per_kind = {k: {"launches": c, "avg_us": round(1000.0 * ms / c, 3)} for k, (c, ms) in tk.items()}
@@ -256,11 +274,12 @@ def main():
 
         # ---- batched (fused) eager and plain per-block FP64 forms --------------------
         def iters_per_s(form, graph, T):
+            # same statistics cadence as the headline
             s2 = state.clone()
-            P.ppd_iterate(plan, s2, y, U, eps, 2, form=form, use_graph=graph, stats=False, **kw)
+            P.ppd_iterate(plan, s2, y, U, eps, 2, form=form, use_graph=graph, x_true=x_true, **kw)
             torch.cuda.synchronize()
             ta = time.perf_counter()
-            P.ppd_iterate(plan, s2, y, U, eps, T, form=form, use_graph=graph, stats=False, **kw)
+            P.ppd_iterate(plan, s2, y, U, eps, T, form=form, use_graph=graph, x_true=x_true, stats_every=every, **kw)
             torch.cuda.synchronize()
             return T / (time.perf_counter() - ta)
 

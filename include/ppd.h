@@ -236,6 +236,21 @@ typedef struct {
   const uint8_t* basis_active;     /* optional DEVICE [9] active set P of SARA
                                       bases (0 = Dirac, p = db-p; steps 18,
                                       23-26); NULL = all bases               */
+  int32_t stats_every;             /* > 0: the statistics of every
+                                      stats_every-th iteration of the call are
+                                      also reduced on the device while the
+                                      iterations run (a stopping test's work,
+                                      no host synchronisation), into
+                                      stats_history if given; 0: only those of
+                                      the last iteration, if stats / residual
+                                      are requested                          */
+  int32_t pad2_;
+  double* stats_history;           /* optional DEVICE [n_iter / stats_every]
+                                      [8 + d]: row k is iteration
+                                      (k + 1) stats_every's rel_change, ||x||,
+                                      SNR dB (NaN without x_true),
+                                      max_j r_j / eps_j, four raw FP64 sums and
+                                      r_j = ||Theta_j G_j F Z x~ - y_j||      */
 } ppd_params;
 
 typedef struct {

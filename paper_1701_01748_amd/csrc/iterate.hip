@@ -17,33 +17,59 @@ int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* v, const 
 namespace {
 
 // One workgroup of 64 threads: statistics of the last iteration.
+// Block residuals r_j = ||Theta_j G_j F Z x~ - y_j|| of the statistics:
+// workgroup j sums block j's segment partials (one pass of 1024 threads
+// over up to 8192 segments, fixed order), or takes the plain form's sum.
+constexpr int STAT_THREADS = 1024, STAT_PER = 8;
+__global__ __launch_bounds__(STAT_THREADS) void k_stats_resid(const double* __restrict__ rpart,
+                                                              const int32_t* __restrict__ bids,
+                                                              const int32_t* __restrict__ boff,
+                                                              const double* __restrict__ res_sq, int use_res_sq,
+                                                              double* __restrict__ out) {
+  __shared__ double red[STAT_THREADS / 64];
+  const int j = blockIdx.x;
+  double r2 = 0.0;
+  if (use_res_sq) {
+    r2 = res_sq[j];
+  } else {
+    const int c0 = boff[j], c1 = boff[j + 1];
+    for (int base = c0; base < c1; base += STAT_THREADS * STAT_PER) {
+      int id[STAT_PER];
+#pragma unroll
+      for (int k = 0; k < STAT_PER; ++k) {
+        const int c = base + int(threadIdx.x) + k * STAT_THREADS;
+        id[k] = c < c1 ? bids[c] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < STAT_PER; ++k) r2 += id[k] >= 0 ? rpart[id[k]] : 0.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r2;
+    __syncthreads();
+    r2 = 0.0;
+    for (int q = 0; q < STAT_THREADS / 64; ++q) r2 += red[q];
+  }
+  if (threadIdx.x == 0) out[8 + j] = sqrt(r2);
+}
+
 // out: [0] rel change, [1] ||x||, [2] SNR dB, [3] max_j r_j / eps_j,
-//      [4..7] raw sums, [8 + j] r_j = ||Theta_j G_j F Z x~ - y_j||.
-__global__ void k_stats(const double* __restrict__ ppart, int nparts, const double* __restrict__ rpart,
-                        const int32_t* __restrict__ bids, const int32_t* __restrict__ boff,
-                        const double* __restrict__ res_sq, int use_res_sq, const double* __restrict__ eps,
-                        int d, int has_truth, double* __restrict__ out) {
-  const int lane = threadIdx.x;
+//      [4..7] raw sums, [8 + j] r_j (from k_stats_resid).
+__global__ __launch_bounds__(256) void k_stats(const double* __restrict__ ppart, int nparts,
+                                               const double* __restrict__ eps, int d, int has_truth,
+                                               double* __restrict__ out) {
+  __shared__ double red[4][4];
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = lane; i < nparts; i += 64)
+  for (int i = threadIdx.x; i < nparts; i += 256)
     for (int k = 0; k < 4; ++k) s[k] += ppart[4 * i + k];
   for (int k = 0; k < 4; ++k)
     for (int o = 32; o > 0; o >>= 1) s[k] += __shfl_xor(s[k], o);
-  double rmax = 0.0;
-  for (int j = 0; j < d; ++j) {
-    double r2;
-    if (use_res_sq) {
-      r2 = res_sq[j];
-    } else {
-      r2 = 0.0;
-      for (int c = boff[j] + lane; c < boff[j + 1]; c += 64) r2 += rpart[bids[c]];
-      for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o);
-    }
-    const double r = sqrt(r2);
-    rmax = fmax(rmax, r / eps[j]);
-    if (lane == 0) out[8 + j] = r;
-  }
-  if (lane == 0) {
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 4; ++k) red[threadIdx.x >> 6][k] = s[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 4; ++k) s[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    double rmax = 0.0;
+    for (int j = 0; j < d; ++j) rmax = fmax(rmax, out[8 + j] / eps[j]);
     out[0] = sqrt(s[0] / s[1]);
     out[1] = sqrt(s[1]);
     out[2] = has_truth ? 20.0 * log10(sqrt(s[3] / s[2])) : __builtin_nan("");
@@ -211,12 +237,13 @@ std::string graph_key(const IterCtx& c) {
 
 }  // namespace
 
-int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq) {
+int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq, double* out) {
   int slot;
   PPD_TRY(timer_begin(p, KK_STATS, &slot));
-  hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, p->stream, p->ppart, primal_partial_count(p), p->rpart,
-                     p->bseg_ids, p->bseg_off_d, p->res_sq, use_res_sq, p->eps_d, p->d, has_truth,
-                     p->stats_d);
+  hipLaunchKernelGGL(k_stats_resid, dim3(p->d), dim3(STAT_THREADS), 0, p->stream, p->rpart, p->bseg_ids,
+                     p->bseg_off_d, p->res_sq, use_res_sq, out);
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(256), 0, p->stream, p->ppart, primal_partial_count(p), p->eps_d, p->d,
+                     has_truth, out);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }
@@ -267,9 +294,18 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   c.primal.eta = prm->eta;
   c.primal.zeta = prm->zeta;
   c.primal.lambda = prm->lambda;
-  // statistics partials of the new iterate only when this call reports them
-  c.primal.part = (stats || residual) ? p->ppart : nullptr;
-  c.dual.rpart = (stats || residual) ? p->rpart : nullptr;
+  // statistics partials of the new iterate only when this call reduces them
+  const int every = prm->stats_every;
+  if (every < 0) return fail(PPD_EINVAL, "ppd_iterate: stats_every must be >= 0");
+  const bool want = stats || residual || every > 0;
+  c.primal.part = want ? p->ppart : nullptr;
+  c.dual.rpart = want ? p->rpart : nullptr;
+  // the periodic reduction: row k of the history, else the plan's buffer
+  auto periodic = [&](int done) -> int {
+    if (every <= 0 || done % every) return PPD_OK;
+    double* out = prm->stats_history ? prm->stats_history + size_t(done / every - 1) * (8 + p->d) : p->stats_d;
+    return stats_finalize(p, prm->x_true != nullptr, prm->form == PPD_FORM_PLAIN, out);
+  };
   c.u = st->u;
   c.W = prm->W;
   c.alpha = float(prm->alpha);
@@ -306,22 +342,27 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
         PPD_HIP(hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0));
         p->graph_key = key;
       }
-      for (int t = 0; t < n_iter; ++t) PPD_HIP(hipGraphLaunch(p->graph_exec, p->stream));
+      for (int t = 0; t < n_iter; ++t) {
+        PPD_HIP(hipGraphLaunch(p->graph_exec, p->stream));
+        PPD_TRY(periodic(t + 1));
+      }
     } else {
       for (int t = 0; t < n_iter; ++t) {
         IterCtx ct = c;
-        if (t + 1 < n_iter) {   // only the last iteration's statistics partials are read
+        const bool read = (t + 1 == n_iter && (stats || residual)) || (every > 0 && (t + 1) % every == 0);
+        if (!read) {   // partials nobody reduces are not formed
           ct.primal.part = nullptr;
           ct.dual.rpart = nullptr;
         }
         PPD_TRY(one_iteration(p, ct));
+        PPD_TRY(periodic(t + 1));
       }
     }
     st->iter += n_iter;
   }
   if (stats || residual) {
     if (n_iter == 0) return fail(PPD_EINVAL, "ppd_iterate: statistics need n_iter >= 1");
-    PPD_TRY(stats_finalize(p, prm->x_true != nullptr, prm->form == PPD_FORM_PLAIN));
+    PPD_TRY(stats_finalize(p, prm->x_true != nullptr, prm->form == PPD_FORM_PLAIN, p->stats_d));
     std::vector<double> h(8 + p->d);
     PPD_HIP(hipMemcpyAsync(h.data(), p->stats_d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, p->stream));
     PPD_HIP(hipStreamSynchronize(p->stream));

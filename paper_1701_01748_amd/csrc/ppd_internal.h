@@ -217,7 +217,7 @@ int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda, 
               const uint8_t* active = nullptr);   // active: DEVICE [9] basis mask, NULL = all
 int sara_synthesis(ppd_plan* p, const float* u, float* out, const float* W);
 
-int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq);
+int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq, double* out);   // out: [8 + d]
 int upload_eps(ppd_plan* p, const double* eps_host);
 
 // host-side setup helpers

@@ -53,7 +53,8 @@ class Params(ctypes.Structure):
                 ("use_graph", c_int32), ("pad_", c_int32), ("y", c_void_p), ("U", c_void_p),
                 ("eps", ctypes.POINTER(c_double)), ("x_true", c_void_p), ("W", c_void_p),
                 ("prox", c_int32), ("n_newton", c_int32), ("block_active", c_void_p),
-                ("basis_active", c_void_p)]
+                ("basis_active", c_void_p), ("stats_every", c_int32), ("pad2_", c_int32),
+                ("stats_history", c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -422,8 +423,11 @@ class PPDState:
 def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49, eta=1.0, zeta=1.0,
                 lam=1.0, alpha=1e-4, mu=1.0, n_itr=1, form=FORM_FUSED, use_graph=False, x_true=None,
                 prox=PROX_FB, n_newton=0, block_active=None, basis_active=None,
-                stats: bool = True, W=None):
-    """Run n_iter iterations of Algorithm 3; returns a statistics dict (or None)."""
+                stats: bool = True, W=None, stats_every: int = 0, stats_history=None):
+    """Run n_iter iterations of Algorithm 3; returns a statistics dict (or None).
+    With stats_every > 0 the statistics of every stats_every-th iteration are
+    also reduced on the device during the call, into stats_history (a float64
+    tensor of n_iter // stats_every rows of 8 + d) if given."""
     import torch
     _need(y, torch.complex64, plan.M, "y")
     _need(U, torch.float64, plan.M, "U")
@@ -439,10 +443,15 @@ def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49
         _need(block_active, torch.uint8, plan.d, "block_active")
     if basis_active is not None:
         _need(basis_active, torch.uint8, 9, "basis_active")
+    if stats_history is not None:
+        if stats_every <= 0:
+            raise ValueError("stats_history needs stats_every > 0")
+        _need(stats_history, torch.float64, (n_iter // stats_every) * (8 + plan.d), "stats_history")
     e, ep = _eps_arg(plan, eps)
     st = State(_ptr(state.x), _ptr(state.xt), _ptr(state.v), _ptr(state.u), _ptr(state.z), state.iter)
     prm = Params(tau, eta, zeta, lam, alpha, mu, n_itr, form, int(use_graph), 0, _ptr(y), _ptr(U), ep,
-                 _ptr(x_true), _ptr(W), int(prox), int(n_newton), _ptr(block_active), _ptr(basis_active))
+                 _ptr(x_true), _ptr(W), int(prox), int(n_newton), _ptr(block_active), _ptr(basis_active),
+                 int(stats_every), 0, _ptr(stats_history))
     out = Stats()
     res = (c_double * plan.d)()
     _check("ppd_iterate", lib().ppd_iterate(plan.handle, ctypes.byref(st), ctypes.byref(prm), int(n_iter),

@@ -181,3 +181,35 @@ def test_per_kernel_timing_counts():
         stream.synchronize()
     assert t.get("fft_rows_fwd", (0, 0.0))[0] == 1
     assert all(t.get(k, (0, 0.0))[0] == 0 for k in per_iter), t
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_periodic_statistics_history(graph):
+    """stats_every = 2 over 6 iterations leaves on the device, row by row,
+    the statistics that separate calls of 2 iterations report (same
+    reductions, bit for bit), eagerly and replayed from a graph."""
+    P = require_gpu()
+    import torch
+    announce(f"periodic statistics graph={graph}")
+    pb, wu, wv = _small_problem()
+    n = pb.x_true.shape[0]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = P.Plan(n, n, wu, wv, pb.block_off, stream=stream)
+        perm, y, U = _gpu_inputs(P, plan, pb)
+        xt = dev(pb.x_true.astype(np.float32), torch.float32)
+        ref = []
+        st = P.PPDState(plan, y)
+        for _ in range(3):
+            s = P.ppd_iterate(plan, st, y, U, pb.eps, 2, eta=pb.eta, x_true=xt, use_graph=graph)
+            ref.append([s["rel_change"], s["x_norm"], s["snr_db"], s["residual_max"]] + list(s["residual"]))
+        hist = torch.zeros(3 * (8 + plan.d), dtype=torch.float64, device="cuda")
+        st2 = P.PPDState(plan, y)
+        s2 = P.ppd_iterate(plan, st2, y, U, pb.eps, 6, eta=pb.eta, x_true=xt, use_graph=graph,
+                           stats_every=2, stats_history=hist)
+        stream.synchronize()
+    h = host(hist).reshape(3, 8 + plan.d)
+    got = np.concatenate([h[:, :4], h[:, 8:]], axis=1)
+    assert np.array_equal(got, np.array(ref)), (got, np.array(ref))
+    assert s2["iter"] == 6 and s2["rel_change"] == ref[-1][0]
+    assert np.array_equal(host(st2.x), host(st.x))
