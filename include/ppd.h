@@ -272,7 +272,10 @@ typedef struct {
  * (PPD_PROX_EXACT; state->z then holds the last prox).  W_i = params->W
  * (identity if NULL).  If stats (HOST) is
  * non-NULL the call synchronises and fills it (and residual[d], HOST, if
- * non-NULL) from FP64 reductions of the last iteration. */
+ * non-NULL) from FP64 reductions of the last iteration.  The statistics
+ * partials are formed only in iterations whose statistics are reduced
+ * (every stats_every-th and the last); a captured graph, which replays one
+ * iteration, forms them in every replay when any are requested. */
 int ppd_iterate(ppd_plan* plan, ppd_state* state, const ppd_params* params, int n_iter,
                 ppd_stats* stats, double* residual);
 
