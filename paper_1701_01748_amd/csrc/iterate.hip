@@ -165,7 +165,7 @@ struct OnStream {
 int data_path(ppd_plan* p, const IterCtx& c) {
   PPD_TRY(fft_cols_forward(p, p->half_f));                  // step 4: a = F Z x~ (rows done)
   if (c.form == PPD_FORM_FUSED && c.prox == PPD_PROX_EXACT) {
-    PPD_TRY(degrid_dual(p, c.dual, p->part));               // step 10 argument w
+    PPD_TRY(degrid_dual(p, c.dual, nullptr));               // step 10 argument w (no Algorithm 2 partials)
     PPD_TRY(secular_solve(p, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.n_newton));  // prox^U_h(w)
     PPD_TRY(grid_dual_exact(p, c.dual));                    // steps 10-12
   } else if (c.form == PPD_FORM_FUSED) {

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
     if (DUAL) {
       const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
       for (int ss = sb; ss <= slast; ++ss) {
-        const double a = wave_sum(act && sg == ss ? qn : 0.0);
+        const double a = part ? wave_sum(act && sg == ss ? qn : 0.0) : 0.0;
         const double r = rpart ? wave_sum(act && sg == ss ? rn : 0.0) : 0.0;
         if (lane == 0) {
           s_q[uwid][ss] += a;
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
         q += s_q[w][k];
         r += s_r[w][k];
       }
-      part[it.seg0 + k] = q;
+      if (part) part[it.seg0 + k] = q;
       if (rpart) rpart[it.seg0 + k] = r;
     }
   }
@@ -688,7 +688,7 @@ __global__ __launch_bounds__(64) void k_degrid8(
       }
       const int slast = __builtin_amdgcn_readlane(sg, min(63, total - 1 - bt * 64));
       for (int ss = sb; ss <= slast; ++ss) {
-        const double a = wave_sum(act && sg == ss ? qn : 0.0);
+        const double a = part ? wave_sum(act && sg == ss ? qn : 0.0) : 0.0;   // Algorithm 2 only
         const double r = rpart ? wave_sum(act && sg == ss ? rn : 0.0) : 0.0;   // statistics only
         if (lane == ss) {
           q_acc += a;
@@ -697,7 +697,7 @@ __global__ __launch_bounds__(64) void k_degrid8(
       }
     }
     if (lane < nseg) {
-      part[seg0 + lane] = q_acc;
+      if (part) part[seg0 + lane] = q_acc;
       if (rpart) rpart[seg0 + lane] = r_acc;
     }
     __builtin_amdgcn_wave_barrier();

@@ -197,7 +197,7 @@ struct DualArgs {
   const uint8_t* active;   // DEVICE [d] block mask of this iteration, NULL = all
   double* rpart = nullptr; // DEVICE [n_segs] residual partials for the statistics, NULL = skip them
 };
-int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out);   // grid_f -> gabuf
+int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out);   // grid_f -> gabuf; part_out NULL: no Algorithm 2 partials
 int grid_plain(ppd_plan* p, const float2* v);                 // v -> grid_a (accumulate)
 int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in);  // dual finish + grid
 
