@@ -83,9 +83,16 @@ def deapod(ny: int, nx: int, beta: float):
 
 
 class Nufft:
-    """Phi = Theta G F Z for one coverage, FP64 (Sec. 2; block rows of Sec. 3.1)."""
+    """Phi = Theta G F Z for one coverage, FP64 (Sec. 2; block rows of Sec. 3.1).
 
-    def __init__(self, wu, wv, ny: int, nx: int, theta=None, beta: float | None = None):
+    ``workers`` > 1 (used only to time the oracle on several host cores):
+    the sparse products G a and G^T v run as row ranges on a thread pool
+    (each output entry is the same dot product as in the single product, so
+    the values are identical) and the FFTs are scipy.fft's with that many
+    workers (the same transform; rounding may differ in the last bits)."""
+
+    def __init__(self, wu, wv, ny: int, nx: int, theta=None, beta: float | None = None,
+                 workers: int | None = None):
         self.ny, self.nx = ny, nx
         self.Ky, self.Kx = grid_shape(ny, nx)
         self.beta = kb_beta() if beta is None else beta
@@ -97,6 +104,33 @@ class Nufft:
         self.scale = sr[:, None] * sc[None, :]
         self.rows = np.mod(np.arange(ny) - ny // 2, self.Ky)
         self.cols = np.mod(np.arange(nx) - nx // 2, self.Kx)
+        self.workers = workers if workers and workers > 1 else None
+        if self.workers:
+            from concurrent.futures import ThreadPoolExecutor
+            self._pool = ThreadPoolExecutor(self.workers)
+            self._Gp = self._row_parts(self.G)
+            self._GTp = self._row_parts(self.GT)
+
+    def _row_parts(self, A):
+        cuts = np.linspace(0, A.shape[0], self.workers + 1).astype(np.int64)
+        return [A[cuts[i]:cuts[i + 1]] for i in range(self.workers)]
+
+    def _matvec(self, A, parts, v):
+        if not self.workers:
+            return A @ v
+        return np.concatenate(list(self._pool.map(lambda B: B @ v, parts)))
+
+    def _fft2(self, g):
+        if not self.workers:
+            return np.fft.fft2(g)
+        import scipy.fft
+        return scipy.fft.fft2(g, workers=self.workers)
+
+    def _ifft2(self, g):
+        if not self.workers:
+            return np.fft.ifft2(g)
+        import scipy.fft
+        return scipy.fft.ifft2(g, workers=self.workers)
 
     # Z: oversample and scale
     def Z(self, x):
@@ -109,11 +143,11 @@ class Nufft:
 
     def fft_grid(self, x):
         """F Z x: the oversampled spectrum of the scaled image."""
-        return np.fft.fft2(self.Z(x))
+        return self._fft2(self.Z(x))
 
     def degrid(self, grid):
         """Theta G a for a spectrum a (Ky x Kx)."""
-        y = self.G @ grid.ravel()
+        y = self._matvec(self.G, getattr(self, "_Gp", None), grid.ravel())
         return y if self.theta is None else self.theta * y
 
     def grid(self, v):
@@ -121,11 +155,11 @@ class Nufft:
         v = np.asarray(v, dtype=np.complex128)
         if self.theta is not None:
             v = self.theta * v
-        return (self.GT @ v).reshape(self.Ky, self.Kx)
+        return self._matvec(self.GT, getattr(self, "_GTp", None), v).reshape(self.Ky, self.Kx)
 
     def ifft_grid_real(self, g):
         """Re Z^H F^H g with F^H = Kx Ky ifft2."""
-        return np.real(self.ZH(np.fft.ifft2(g) * (self.Kx * self.Ky)))
+        return np.real(self.ZH(self._ifft2(g) * (self.Kx * self.Ky)))
 
     def phi(self, x):
         return self.degrid(self.fft_grid(x))

@@ -6,7 +6,7 @@ iteration, Sec. 5.1), so the active sets are all data blocks and all bases.
 With U = 1, mu = 1 and one sub-iteration the data dual step is the Euclidean
 l2-ball step of the non-preconditioned PD algorithm.
 
-Reading of step 10 (whose printed form mixes dual and data scales):
+Reading of the data-dual update (whose printed form mixes dual and data scales):
   w_j   = U_j^{-1} v_j + Theta_j G_j M_j a
   vbar_j = U_j (w_j - prox^{U_j}_{h_j}(w_j)),
 the generalised Moreau decomposition (Sec. 4.1) with alpha = 1, where the
@@ -71,7 +71,9 @@ def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
     op: ``oracle.nufft.Nufft``; y, U: (M,) data and preconditioner; eps: (d,)
     l2 bounds; block_off: (d+1,) contiguous block offsets; W: optional (9, Ny,
     Nx) re-weights (identity when None).  Returns a list of per-iteration
-    records (SNR when x_true is given, relative change, block residuals).
+    records: SNR when x_true is given, the relative change
+    ||x_t - x_{t-1}|| / ||x_t||, ||x_t||, and the block residuals
+    ||Phi_j x~ - y_j|| at the x~ the iteration started from.
     If ``trace`` is a list, each iteration appends what decides its active
     sets -- the clip margins |u + Psi^H x~| - alpha, the arguments of P_C and
     which Algorithm 2 steps project -- i.e. the pieces on which the iteration
@@ -79,23 +81,23 @@ def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
     ``active`` (randomised Algorithm 3): None (every block and basis each
     iteration) or a sequence of T pairs (block_mask (d,), basis_mask (9,)):
     an inactive block keeps v_j (and its Algorithm 2 iterate), an inactive
-    basis keeps u_i (steps 14-17, 23-26); the random draws are inputs."""
+    basis keeps u_i; the random draws are inputs."""
     p = params
     y = np.asarray(y, np.complex128)
     U = np.asarray(U, np.float64)
     hist = []
     for t in range(T):
         bmask, pmask = (None, None) if active is None else active[t]
-        a = op.fft_grid(state.xt)                          # step 4: a = F Z x tilde
+        a = op.fft_grid(state.xt)                          # a = F Z x tilde
         Ga = op.degrid(a)                                  # Theta_j G_j M_j a, all j
         v_new = state.v.copy()
         z_new = state.z.copy()
         res = []
         sets_proj = []
-        for j in range(len(block_off) - 1):                # steps 9-13, all blocks
+        for j in range(len(block_off) - 1):                # every data block
             s = slice(int(block_off[j]), int(block_off[j + 1]))
             res.append(np.linalg.norm(Ga[s] - y[s]))
-            if bmask is not None and not bmask[j]:         # steps 14-17: v_j, z_j kept
+            if bmask is not None and not bmask[j]:         # inactive: v_j, z_j kept
                 sets_proj.append(())
                 continue
             w = state.v[s] / U[s] + Ga[s]
@@ -112,31 +114,33 @@ def iterate(op, y, U, eps, block_off, params: Params, state: State, T: int,
                     proj.append(bool(np.linalg.norm(q - y[s]) > eps[j]))
                     zz = prox.proj_B(q, y[s], eps[j])
                 sets_proj.append(tuple(proj))
-            vbar = U[s] * (w - z)                          # step 10
-            v_new[s] = state.v[s] + p.lam * (vbar - state.v[s])   # step 11
+            vbar = U[s] * (w - z)                          # generalised Moreau identity
+            v_new[s] = state.v[s] + p.lam * (vbar - state.v[s])   # relaxation
             z_new[s] = z
-        vt = op.grid(v_new)                                # step 12, summed over j
+        vt = op.grid(v_new)                                # G^H Theta^H v, summed over j
         coef = sara.analysis(state.xt, p.levels)           # Psi_i^H x tilde
         if W is not None:
             coef = W * coef
-        ubar = prox.clip_dual(state.u + coef, p.alpha)     # step 19
-        u_new = state.u + p.lam * (ubar - state.u)         # step 20
-        if pmask is not None:                              # steps 23-26: u_i kept
+        ubar = prox.clip_dual(state.u + coef, p.alpha)     # (I - S_alpha)
+        u_new = state.u + p.lam * (ubar - state.u)         # relaxation
+        if pmask is not None:                              # inactive bases: u_i kept
             keep = ~np.asarray(pmask, dtype=bool)
             u_new[keep] = state.u[keep]
-        ut = sara.synthesis(u_new if W is None else W * u_new, p.levels)  # step 21, summed
+        ut = sara.synthesis(u_new if W is None else W * u_new, p.levels)  # Psi W u, summed
         arg = state.x - p.tau * (p.eta * op.ifft_grid_real(vt) + p.zeta * ut)
-        xbar = prox.proj_C(arg)                            # step 28
+        xbar = prox.proj_C(arg)                            # P_C of the primal step
         if trace is not None:
             trace.append({"clip": np.abs(state.u + coef) - p.alpha, "pos": arg,
                           "proj": tuple(sets_proj)})
         x_prev = state.x
-        x_new = x_prev + p.lam * (xbar - x_prev)           # step 29
-        xt_new = 2.0 * xbar - x_prev                       # step 30
+        x_new = x_prev + p.lam * (xbar - x_prev)           # relaxation
+        xt_new = 2.0 * xbar - x_prev                       # x tilde
         state.x, state.xt, state.v, state.u, state.z = x_new, xt_new, v_new, u_new, z_new
         state.it += 1
+        x_norm = float(np.linalg.norm(x_new))
         rec = {"it": state.it,
-               "rel_change": float(np.linalg.norm(x_new - x_prev) / max(np.linalg.norm(x_new), 1e-300)),
+               "rel_change": float(np.linalg.norm(x_new - x_prev) / max(x_norm, 1e-300)),
+               "x_norm": x_norm,
                "residual": res}
         if x_true is not None:
             rec["snr"] = float(snr_db(x_true, x_new))

@@ -23,7 +23,7 @@ def soft(z, alpha: float):
 
 
 def clip_dual(z, alpha: float):
-    """(I - S_alpha)(z), the l1 dual update of Algorithm 3, step 19."""
+    """(I - S_alpha)(z), the clip of the l1 dual update of Algorithm 3."""
     z = np.asarray(z)
     return z - soft(z, alpha)
 

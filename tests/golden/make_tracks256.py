@@ -4,8 +4,9 @@
 
 256 x 256 image, 65536 points on 36 elliptical tracks, blocks of 8000, 12000,
 20000 and 25536 points, 30 dB input SNR; PPD with 5 Algorithm 2 iterations
-(Sec. 5.1 uses 1, 5 and 50) and PD (U = 1), 500 iterations each.  Calls only
-the oracle and the seeded input generators.  Output: tracks256_snr.json.
+(Sec. 5.1 uses 1, 5 and 50), PPD with 50, and PD (U = 1), 500 iterations
+each.  Calls only the oracle and the seeded input generators.  Output:
+tracks256_snr.json (keys "ppd", "ppd_nitr50" and "pd").
 """
 import json
 import os
@@ -27,9 +28,11 @@ def main(T: int = 500):
     pb = P.problem_from_inputs(inp, power_tol=1e-9)
     out = {"workload": w.name, "iterations": T, "n_itr": w.n_itr, "eta_ppd": pb.eta, "eta_pd": pb.eta_pd,
            "sigma": pb.sigma, "eps": pb.eps.tolist()}
-    for name, U, eta in [("ppd", pb.U, pb.eta), ("pd", np.ones_like(pb.U), pb.eta_pd)]:
+    runs = [("ppd", pb.U, pb.eta, w.n_itr), ("pd", np.ones_like(pb.U), pb.eta_pd, 1),
+            ("ppd_nitr50", pb.U, pb.eta, 50)]
+    for name, U, eta, n_itr in runs:
         st = O.init_state(w.n, w.n, pb.y)
-        prm = O.Params(eta=eta, mu=1.0 / U.max(), n_itr=w.n_itr if name == "ppd" else 1)
+        prm = O.Params(eta=eta, mu=1.0 / U.max(), n_itr=n_itr)
         hist = O.iterate(pb.op, pb.y, U, pb.eps, pb.block_off, prm, st, T, x_true=pb.x_true)
         out[name] = {"snr_db": [h["snr"] for h in hist],
                      "residual_over_eps_final": (np.array(hist[-1]["residual"]) / pb.eps).tolist(),

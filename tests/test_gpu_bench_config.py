@@ -1,9 +1,19 @@
 """The benchmark's own workload at full size and in its launch
 configuration: 512^2 image, 1.3M visibilities in 16 uneven blocks, plan
 defaults (8 x 8 tiles, 128-point items), one Algorithm 2 step per iteration.
-Fused iterations, first launched eagerly on the two streams and then
-replayed from a HIP graph, are compared element by element with the FP64
-oracle (Algorithm 3)."""
+
+* Fused iterations, first launched eagerly on the two streams and then
+  replayed from a HIP graph, element by element against the FP64 oracle
+  (Algorithm 3), with the statistics of every iteration against the
+  oracle's records.
+* 200 iterations (the length the reconstruction SNR bar is stated for)
+  against the oracle's stored trajectory (tests/golden/make_ppd512.py): SNR
+  within 0.05 dB every 25 iterations, eagerly and replayed from a graph,
+  with the statistics reduced on the device every 25 iterations as in the
+  benchmark."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -12,18 +22,29 @@ from oracle import ppd as O
 from oracle import problem as oprob
 from oracle import sara as osara
 
-from gpu_util import announce, assert_op_close, dev, host, require_gpu
+from gpu_util import announce, assert_op_close, check_stats, check_trajectory, dev, host, require_gpu
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ppd512_traj.json")
+_CACHE = {}
+
+
+def _problem():
+    """The ppd512 inputs and the oracle's problem (built once per module)."""
+    if "pb" not in _CACHE:
+        inp = synth.make_inputs(synth.WORKLOADS["ppd512"])
+        _CACHE["inp"] = inp
+        _CACHE["pb"] = oprob.problem_from_inputs(inp, with_eta=False)
+    return _CACHE["inp"], _CACHE["pb"]
 
 
 def test_ppd512_bench_configuration_matches_oracle():
     P = require_gpu()
     import torch
     announce("ppd512 full size, plan defaults, eager then graph")
-    inp = synth.make_inputs(synth.WORKLOADS["ppd512"])
+    inp, pb = _problem()
     n = inp.workload.n
-    pb = oprob.problem_from_inputs(inp, with_eta=False)
     # a step size from a few oracle power iterations: parity does not depend
     # on its exact value, only on both sides using the same one
     eta = 1.0 / oprob.power_norm(pb.op, pb.U, inp.power_start, tol=1e-3, max_iter=10)
@@ -34,12 +55,15 @@ def test_ppd512_bench_configuration_matches_oracle():
         perm = plan.permutation()
         y = dev(pb.y[perm].astype(np.complex64), torch.complex64)
         U = dev(pb.U[perm], torch.float64)
+        xt = dev(pb.x_true.astype(np.float32), torch.float32)
         st = P.PPDState(plan, y)
         ost = O.init_state(n, n, pb.y)
         prm = O.Params(eta=eta, mu=1.0, n_itr=1)
         for graph in (False, True):
-            O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, ost, 2)
-            s = P.ppd_iterate(plan, st, y, U, pb.eps, 2, eta=eta, mu=1.0, n_itr=1, use_graph=graph)
+            recs = O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, ost, 2, x_true=pb.x_true)
+            hist = torch.zeros(2 * (8 + plan.d), dtype=torch.float64, device="cuda")
+            s = P.ppd_iterate(plan, st, y, U, pb.eps, 2, eta=eta, mu=1.0, n_itr=1, use_graph=graph, x_true=xt,
+                              stats_every=1, stats_history=hist)
             stream.synchronize()
             assert s["iter"] == ost.it
             mode = "graph" if graph else "eager"
@@ -50,3 +74,22 @@ def test_ppd512_bench_configuration_matches_oracle():
             u_scale = np.abs(osara.analysis(ost.xt)).max()
             du = np.abs(host(st.u) - ost.u).max()
             assert du <= 1e-5 * u_scale, f"u after {ost.it} ({mode}): {du:.3e} vs scale {u_scale:.3e}"
+            check_stats(host(hist).reshape(2, 8 + plan.d), recs, pb.y, pb.block_off, pb.eps, f"ppd512 {mode}")
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_ppd512_200_iterations_vs_oracle_trajectory(graph):
+    P = require_gpu()
+    import torch
+    if not os.path.exists(GOLDEN):
+        pytest.fail("missing golden file: run tests/golden/make_ppd512.py")
+    with open(GOLDEN) as f:
+        ref = json.load(f)
+    announce(f"ppd512 200 iterations vs oracle trajectory graph={graph}")
+    inp, pb = _problem()
+    assert np.allclose(pb.eps, ref["eps"], rtol=1e-12) and ref["M"] == pb.y.size
+    n = inp.workload.n
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = P.Plan(n, n, inp.wu[0], inp.wv[0], inp.block_off, stream=stream)
+        check_trajectory(P, plan, pb, plan.permutation(), ref, graph, f"ppd512 graph={graph}")

@@ -1,8 +1,10 @@
 """The 8-channel workload at full size (512^2, 1M points per channel,
 channel frequencies scaled by nu/nu0 in [0.9, 1.1]): sampled Phi outputs of
 every channel against the FP64 oracle, the adjoint identity per channel,
-and the gradients of the multi-channel data fidelity and of K = 10 unrolled
-PPD iterations (timed; their parity is the small-size oracle tests')."""
+the gradient of the multi-channel data fidelity (timed) and its parity with
+the oracle's on sampled points (closed form and FP64 difference quotient),
+and the gradients of K = 10 unrolled PPD iterations (timed; their parity is
+the small-size oracle tests')."""
 import math
 import time
 
@@ -56,20 +58,55 @@ def test_multichannel_full_size():
     torch.cuda.synchronize()
     t_mc = (time.perf_counter() - t0) / 5
     g = xg.grad.detach()
-    # the gradient is 2 Re sum_c Phi_c^H (Phi_c x - y_c): check it along a random direction
-    # against the FP64 difference quotient of the loss (the loss is quadratic: exact up to rounding)
-    d = torch.randn_like(x, generator=torch.Generator("cuda").manual_seed(99))
-    h = 1e-2 * float(x.abs().max())
+    assert torch.isfinite(g).all()
+    # Parity of the gradient with the oracle, on the fidelity restricted to a
+    # sampled subset S_c of each channel's points (the full 8 x 1M oracle is
+    # out of reach): L_S(x) = sum_c sum_{e in S_c} |(Phi_c x)_e - y_ce|^2.
+    # GPU: forward Phi and backward Re Phi^H on the masked residual (the
+    # library's kernels through autograd).  Oracle: its closed form
+    # 2 Re sum_c Phi_Sc^H (Phi_Sc x - y_Sc) element by element, and the FP64
+    # central difference of its own L_S (quadratic, so exact up to rounding)
+    # along a random direction with h = 1e-3.  Tolerance: the operator bar
+    # 1e-5 carried through the residual, 1e-5 (1 + ||Phi_S x|| / ||Phi_S x - y_S||).
+    xs = (0.9 * x).clone().requires_grad_(True)
+    xs64 = host(0.9 * x).astype(np.float64)
+    g_or = np.zeros((n, n))
+    r_norm2, px_norm2 = 0.0, 0.0
+    ops = []
+    total = 0.0
+    for c, (p, yc) in enumerate(zip(plans, ys)):
+        perm = p.permutation()
+        pick = np.sort(np.random.default_rng(200 + c).choice(p.M, 2000, replace=False))   # user order
+        inv = np.empty(p.M, np.int64)
+        inv[perm] = np.arange(p.M)
+        mask = torch.zeros(p.M, dtype=torch.float32, device="cuda")
+        mask[torch.as_tensor(inv[pick], device="cuda")] = 1.0
+        r = A.phi(p, xs) - yc
+        total = total + ((r.real ** 2 + r.imag ** 2) * mask).sum()
+        yu = np.empty(p.M, np.complex64)
+        yu[perm] = host(yc)
+        op = onf.Nufft(inp.wu[c][pick], inp.wv[c][pick], n, n)
+        yS = yu[pick].astype(np.complex128)
+        res = op.phi(xs64) - yS
+        g_or += 2.0 * op.phit(res)
+        r_norm2 += float(np.sum(np.abs(res) ** 2))
+        px_norm2 += float(np.sum(np.abs(op.phi(xs64)) ** 2))
+        ops.append((op, yS))
+    total.backward()
+    g_gpu = host(xs.grad).astype(np.float64)
+    tol = 1e-5 * (1.0 + math.sqrt(px_norm2 / r_norm2))
+    e_g = rel_err(g_gpu, g_or)
+    assert e_g <= tol, (e_g, tol)
+    dirn = np.random.default_rng(98).standard_normal((n, n))
+    hfd = 1e-3
 
-    def loss64(xv):
-        s = 0.0
-        for p, y in zip(plans, ys):
-            rr = P.ppd_phi(p, xv).to(torch.complex128) - y.to(torch.complex128)
-            s += float((rr.abs() ** 2).sum())
-        return s
-    fd = (loss64((0.9 * x + h * d).contiguous()) - loss64((0.9 * x - h * d).contiguous())) / (2 * h)
-    ad = float((g.double() * d.double()).sum())
-    assert abs(ad - fd) <= 1e-3 * abs(fd) + 1e-6 * float(g.double().norm() * d.double().norm()), (ad, fd)
+    def loss_or(xv):
+        return sum(float(np.sum(np.abs(op.phi(xv) - yS) ** 2)) for op, yS in ops)
+    fd = (loss_or(xs64 + hfd * dirn) - loss_or(xs64 - hfd * dirn)) / (2.0 * hfd)
+    ad = float(np.sum(g_gpu * dirn))
+    assert abs(ad - fd) <= tol * np.linalg.norm(g_or) * np.linalg.norm(dirn), (ad, fd)
+    print(f"[multichannel] sampled-fidelity gradient vs oracle: rel err {e_g:.2e} (tol {tol:.2e}); "
+          f"directional derivative {ad:.6e} vs oracle difference quotient {fd:.6e}", flush=True)
     # K = 10 unrolled PPD iterations on channel 0, gradient w.r.t. x0 and y
     plan = plans[0]
     U = P.ppd_uniform_weights(plan)

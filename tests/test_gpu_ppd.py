@@ -78,6 +78,10 @@ def test_first_iteration_closed_form_gpu():
 
 
 def test_graph_replay_matches_eager():
+    """A replayed graph runs the same kernels with the same fixed summation
+    orders as eager launches (only the stream each branch runs on differs):
+    the iterates agree bit for bit, replay after replay, with eager work in
+    between."""
     P = require_gpu()
     import torch
     announce("graph replay vs eager")
@@ -93,8 +97,8 @@ def test_graph_replay_matches_eager():
             P.ppd_iterate(plan, a, y, U, pb.eps, 5, eta=pb.eta, use_graph=False)
             P.ppd_iterate(plan, b, y, U, pb.eps, 5, eta=pb.eta, use_graph=True)
             stream.synchronize()
-            assert rel_err(host(b.x), host(a.x)) < 1e-6, rep
-            assert rel_err(host(b.v), host(a.v)) < 1e-6, rep
+            for k in ("x", "xt", "v", "u", "z"):
+                assert np.array_equal(host(getattr(b, k)), host(getattr(a, k))), (rep, k)
 
 
 def test_workload64_snr_parity():

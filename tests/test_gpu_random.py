@@ -1,5 +1,5 @@
 """GPU parity of randomised Algorithm 3 (active sets of blocks and SARA
-bases drawn per iteration, steps 8, 14-17 and 23-26) against the FP64
+bases drawn per iteration) against the FP64
 oracle fed the same draws."""
 import numpy as np
 import pytest

@@ -1,9 +1,12 @@
 """The 2048x2048, 20M-visibility, 64-block workload (on-the-fly
 Kaiser-Bessel weights): sampled operator outputs against the FP64 oracle at
 full size, the adjoint identity at full size, elementwise iteration parity on
-the 512x512 crop problem at the same visibility density (oracle), and a
-200-iteration PPD run at full size."""
+the 512x512 crop problem at the same visibility density (oracle), the crop
+problem's 200-iteration SNR trajectory against the oracle's
+(tests/golden/make_crop2048.py), and a 200-iteration PPD run at full size."""
+import json
 import math
+import os
 import time
 
 import numpy as np
@@ -15,10 +18,12 @@ from oracle import ppd as O
 from oracle import problem as oprob
 from oracle import sara as osara
 
-from gpu_util import announce, assert_op_close, dev, host, rel_err, require_gpu
+from gpu_util import announce, assert_op_close, check_trajectory, dev, host, rel_err, require_gpu
 
 pytestmark = pytest.mark.gpu
 
+CROP_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "crop2048_traj.json")
+CROP_SEED = 901
 _BIG = {}
 
 
@@ -26,6 +31,14 @@ def _big():
     if "inp" not in _BIG:
         _BIG["inp"] = synth.make_inputs(synth.WORKLOADS["ppd2048"])
     return _BIG["inp"]
+
+
+def _crop():
+    """The 512^2 crop problem's inputs and oracle problem (built once)."""
+    if "crop" not in _BIG:
+        c = synth.crop_inputs(_big(), 512, 16, seed=CROP_SEED)
+        _BIG["crop"] = (c, oprob.problem_from_inputs(c, with_eta=False))
+    return _BIG["crop"]
 
 
 def test_phi_sampled_and_adjoint_full_size():
@@ -61,8 +74,7 @@ def test_crop_problem_iterations_match_oracle():
     P = require_gpu()
     import torch
     announce("ppd2048 crop 512 parity")
-    c = synth.crop_inputs(_big(), 512, 16, seed=901)
-    pb = oprob.problem_from_inputs(c, with_eta=False)
+    c, pb = _crop()
     n = 512
     plan = P.Plan(n, n, c.wu[0], c.wv[0], c.block_off)
     perm = plan.permutation()
@@ -79,6 +91,25 @@ def test_crop_problem_iterations_match_oracle():
     assert_op_close(host(st.v), ost.v[perm], what="v")
     u_scale = np.abs(osara.analysis(ost.xt)).max()
     assert np.abs(host(st.u) - ost.u).max() <= 1e-5 * u_scale
+
+
+def test_crop_problem_200_iterations_vs_oracle_trajectory():
+    """200 fused iterations of the crop problem with the oracle's step size:
+    SNR within 0.05 dB of the oracle's every 25 iterations."""
+    P = require_gpu()
+    import torch
+    if not os.path.exists(CROP_GOLDEN):
+        pytest.fail("missing golden file: run tests/golden/make_crop2048.py")
+    with open(CROP_GOLDEN) as f:
+        ref = json.load(f)
+    assert ref["crop_seed"] == CROP_SEED
+    announce("ppd2048 crop 512, 200 iterations vs oracle trajectory")
+    c, pb = _crop()
+    assert np.allclose(pb.eps, ref["eps"], rtol=1e-12) and ref["M"] == pb.y.size
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = P.Plan(512, 512, c.wu[0], c.wv[0], c.block_off, stream=stream)
+        check_trajectory(P, plan, pb, plan.permutation(), ref, False, "crop2048")
 
 
 def test_ppd2048_200_iterations():

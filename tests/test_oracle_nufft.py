@@ -116,3 +116,18 @@ def test_G_has_64_nonzeros_per_row():
     G = nf.build_G(wu, wv, 32, 32, nf.kb_beta())
     assert np.all(np.diff(G.indptr) == 64)
     assert np.all(G.data > 0)
+
+
+def test_threaded_operator_matches_single_threaded():
+    """The oracle's multi-core option (used only to time it): row ranges of
+    the sparse products give the same values bit for bit; scipy.fft's
+    transforms agree with numpy's to rounding."""
+    x, wu, wv, off = synth.small_case(32, 3000, seed=5)
+    a = nf.Nufft(wu, wv, 32, 32)
+    b = nf.Nufft(wu, wv, 32, 32, workers=4)
+    g = a.fft_grid(x)
+    assert np.array_equal(a.degrid(g), b.degrid(g))
+    v = a.degrid(g)
+    assert np.array_equal(a.grid(v), b.grid(v))
+    assert np.abs(b.fft_grid(x) - g).max() <= 1e-13 * np.abs(g).max()
+    assert np.abs(b.phit(v) - a.phit(v)).max() <= 1e-13 * np.abs(a.phit(v)).max()

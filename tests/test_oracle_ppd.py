@@ -224,6 +224,45 @@ def test_weighted_iteration_identity_and_zero():
     assert np.abs(runs["none"].u).max() > 0.0
 
 
+def test_snr_db_closed_forms():
+    """SNR = 20 log10(||x_true|| / ||x_true - x||) (Sec. 5) on cases with
+    exact values: a 10% uniform error is 20 dB, an error as large as the
+    image 0 dB, an error ten times the image -20 dB."""
+    xt = np.ones((4, 4))
+    assert abs(O.snr_db(xt, 0.9 * xt) - 20.0) < 1e-12
+    assert abs(O.snr_db(np.array([[3.0, 4.0]]), np.array([[3.0, 4.5]])) - 20.0) < 1e-12
+    assert abs(O.snr_db(xt, np.zeros((4, 4)))) < 1e-12
+    assert abs(O.snr_db(xt, 2.0 * xt)) < 1e-12
+    assert abs(O.snr_db(xt, -9.0 * xt) - (-20.0)) < 1e-12
+
+
+def test_reweighted_schedule():
+    """Algorithm 1 with two re-weightings: solve 0 with W = I; solve k uses
+    W = omega_k / (omega_k + |Psi^H x|) from the image x (not x tilde) that
+    solve k-1 ended with, omega_k = 0.25^k 1e-2 (Sec. 5.1: 2.5e-3, then
+    6.25e-4); every solve warm-starts from the state the previous one left.
+    Written out solve by solve and compared bit for bit; the readings a slip
+    would produce (weights from x tilde, omega decayed one step late) are
+    checked to differ, so the comparison can tell them apart."""
+    pb = _weighted_problem(seed=75)
+    n = pb.x_true.shape[0]
+    prm = O.Params(eta=pb.eta)
+    st = O.init_state(n, n, pb.y)
+    hists, W = O.reweighted(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, st, 2, 4)
+    assert len(hists) == 3 and all(len(h) == 4 for h in hists)
+    ref = O.init_state(n, n, pb.y)
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, ref, 4)
+    W1 = 2.5e-3 / (2.5e-3 + np.abs(sara.analysis(ref.x)))
+    W1_slip_xt = 2.5e-3 / (2.5e-3 + np.abs(sara.analysis(ref.xt)))
+    W1_slip_omega = 1e-2 / (1e-2 + np.abs(sara.analysis(ref.x)))
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, ref, 4, W=W1)
+    W2 = 6.25e-4 / (6.25e-4 + np.abs(sara.analysis(ref.x)))
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, ref, 4, W=W2)
+    assert np.array_equal(W, W2)
+    assert np.array_equal(st.x, ref.x) and np.array_equal(st.u, ref.u) and np.array_equal(st.v, ref.v)
+    assert not np.allclose(W1, W1_slip_xt) and not np.allclose(W1, W1_slip_omega)
+
+
 def test_reweighted_outer_loop_improves_snr():
     """Algorithm 1 on the 64x64 workload: each re-weighted solve, warm-started,
     ends at a higher SNR than the unweighted solve of the same total length
@@ -270,7 +309,7 @@ def test_exact_prox_is_limit_of_algorithm2():
     assert np.linalg.norm(a.z - b.z) <= 1e-6 * np.linalg.norm(a.z)
 
 
-# ---- randomised active sets (Algorithm 3 steps 8, 14-17, 23-26) -----------
+# ---- randomised active sets of blocks and bases (Algorithm 3) -------------
 
 def test_all_active_masks_equal_full_iteration():
     pb = _weighted_problem(seed=76)
