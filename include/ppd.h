@@ -104,6 +104,9 @@ typedef struct {
   double kb_beta;
   size_t device_bytes;        /* device memory of the plan's buffers (allocated,
                                  or carved from the caller's workspace)         */
+  int32_t persistent;         /* 1 if the Algorithm 2 middle steps can run as
+                                 one persistent launch (ppd_params.persistent) */
+  int32_t pad_;
 } ppd_plan_info;
 int ppd_plan_get_info(const ppd_plan* plan, ppd_plan_info* info /* HOST */);
 
@@ -125,14 +128,14 @@ int ppd_plan_permute(ppd_plan* plan, int direction, const void* in, void* out, i
 int ppd_phi(ppd_plan* plan, const float* x, float* y, int order);
 
 /* x = Re(Z^H F^H G^H Theta^H y), the adjoint of ppd_phi for a real image
- * (Sec. 2; step 12 and the sum of step 28 of Algorithm 3).
+ * (Sec. 2; the gridding and the primal step of Algorithm 3).
  * y: [M] complex64 in the given order.  x: [ny][nx] float32. */
 int ppd_phit(ppd_plan* plan, const float* y, float* x, int order);
 
 /* ---- SARA sparsity operator (Sec. 5.1: Dirac + Daubechies 1..8) -------- */
 #define PPD_SARA_ANALYSIS  0   /* out[9][ny][nx] = Psi^H in  (in: image)        */
 #define PPD_SARA_SYNTHESIS 1   /* out[ny][nx] = Psi in       (in: [9][ny][nx])  */
-#define PPD_SARA_DUAL      2   /* Algorithm 3 steps 19-21 with W = I:
+#define PPD_SARA_DUAL      2   /* SARA dual update of Algorithm 3, W = I:
                                   u <- u + lambda (clip(u + Psi^H in, +-alpha) - u),
                                   out[ny][nx] = Psi u  (in: image, u_inout used) */
 /* Psi = (1/3)[I, W_1, .., W_8] with W_p the orthonormal periodised 2D
@@ -209,6 +212,9 @@ typedef struct {
 #define PPD_PROX_EXACT 1   /* prox^U_h exactly (ppd_prox_metric, n_newton
                               Newton steps); fused form only                  */
 
+#define PPD_PERSIST_AUTO 0
+#define PPD_PERSIST_OFF  1
+
 typedef struct {
   double tau, eta, zeta, lambda;   /* Algorithm 3 step sizes and relaxation   */
   double alpha;                    /* l1 dual clip kappa ||Psi W||_S^2        */
@@ -229,13 +235,29 @@ typedef struct {
   int32_t prox;                    /* PPD_PROX_* (0 = Algorithm 2)            */
   int32_t n_newton;                /* Newton steps for PPD_PROX_EXACT (0 -> 12) */
   const uint8_t* block_active;     /* optional DEVICE [d] active set D of the
-                                      iterations of this call (Algorithm 3
-                                      steps 8, 14-17): block j's v_j and z_j
+                                      iterations of this call (randomised
+                                      Algorithm 3): block j's v_j and z_j
                                       are updated only where nonzero; NULL =
                                       all blocks; fused form only            */
   const uint8_t* basis_active;     /* optional DEVICE [9] active set P of SARA
-                                      bases (0 = Dirac, p = db-p; steps 18,
-                                      23-26); NULL = all bases               */
+                                      bases (0 = Dirac, p = db-p; randomised
+                                      Algorithm 3); NULL = all bases         */
+  int32_t persistent;              /* PPD_PERSIST_AUTO (0): with n_itr > 1
+                                      in the fused form and Algorithm 2, the
+                                      n_itr - 1 middle steps run as one
+                                      persistent launch with the per-point
+                                      state in registers and a bounded grid
+                                      barrier per step, when the plan's
+                                      points fit the device at once (about
+                                      2M visibilities) and no 2048 consecutive
+                                      plan-order points span more than 4
+                                      blocks; PPD_PERSIST_OFF (1): one launch
+                                      pair per step                          */
+  int32_t spin_limit;              /* polls of a persistent grid barrier
+                                      before it gives up (0: 2^20); a give-up
+                                      makes every workgroup finish and the
+                                      next call that reads statistics return
+                                      PPD_EDEVICE                            */
   int32_t stats_every;             /* > 0: the statistics of every
                                       stats_every-th iteration of the call are
                                       also reduced on the device while the
@@ -265,7 +287,7 @@ typedef struct {
  * is updated each iteration unless params->block_active / basis_active name
  * active subsets (the randomised variant; the masks are read on the device
  * at each iteration, so the caller may rewrite them between calls).
- * Step 10 is read as
+ * The data-dual update is read as
  * vbar_j = U_j (w_j - prox^U_h(w_j)), w_j = U_j^{-1} v_j + Theta_j G_j a,
  * with the prox approximated by n_itr Algorithm 2 iterations warm-started
  * from state->z (PPD_PROX_FB), or computed as by ppd_prox_metric
@@ -274,8 +296,9 @@ typedef struct {
  * non-NULL the call synchronises and fills it (and residual[d], HOST, if
  * non-NULL) from FP64 reductions of the last iteration.  The statistics
  * partials are formed only in iterations whose statistics are reduced
- * (every stats_every-th and the last); a captured graph, which replays one
- * iteration, forms them in every replay when any are requested. */
+ * (every stats_every-th and the last); with use_graph the plan keeps two
+ * captured iterations, one forming them and one not, and replays each
+ * where it applies. */
 int ppd_iterate(ppd_plan* plan, ppd_state* state, const ppd_params* params, int n_iter,
                 ppd_stats* stats, double* residual);
 

@@ -1,4 +1,4 @@
-// Data-fidelity dual update (Algorithm 3 steps 10-11) and Algorithm 2,
+// Data-fidelity dual update of Algorithm 3 and Algorithm 2,
 // FP64: the standalone ellipsoid projection entry point, the unfused
 // per-block ("plain") form of the dual update, and the uniform-weighting
 // preconditioner (inverse local sampling density, Sec. 4.3).
@@ -34,11 +34,11 @@ __global__ __launch_bounds__(64 * NW) void k_alg2(
     const double2* __restrict__ w, const float2* __restrict__ v, const float2* __restrict__ ga,
     const float2* __restrict__ y, const double* __restrict__ U,
     double2* __restrict__ z, double mu, const double2* __restrict__ bfac, const uint8_t* __restrict__ active,
-    double* __restrict__ part_out) {
+    double* __restrict__ part_out, XcdSplit xs) {
   __shared__ ItemTab tab;
   __shared__ double s_q[NW][MAX_ITEM_SEGS];
-  const int ii = xcd_remap(blockIdx.x, gridDim.x);
-  if (ii >= n_items) return;
+  const int ii = xcd_unit(blockIdx.x, xs);
+  if (ii < 0 || ii >= n_items) return;
   const Item it = items[ii];
   const int lane = threadIdx.x & 63;
   const int uwid = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(64 * NW) void k_alg2(
       double2 ze = z[pi];
       const double mU = mu * Ue;
       const float2 ye = y[pi];
-      // randomised updates (Algorithm 3 steps 14-17): an inactive block keeps z
+      // randomised updates of Algorithm 3: an inactive block keeps z
       if (mode != 0 && (!active || active[tab.block[sg]])) {
         const double2 bf = bfac[tab.block[sg]];
         const double qx = ze.x - mU * (ze.x - we.x), qy = ze.y - mU * (ze.y - we.y);
@@ -131,6 +131,159 @@ __global__ __launch_bounds__(BF_THREADS) void k_block_factors(const double* __re
     for (int q = 0; q < BF_THREADS / 64; ++q) t += red[q];
     const double r = sqrt(t), e = eps[j];
     bfac[j] = r > e ? make_double2(e / r, 0.0) : make_double2(1.0, 1.0);
+  }
+}
+
+// ---- persistent middle steps of Algorithm 2 ---------------------------------
+// One launch runs the n_itr - 1 middle forward-backward steps of every block
+// with the per-point state (w, z, U, y) held in registers: workgroup g owns
+// the PA_CHUNK plan-order points from g PA_CHUNK (blocks are contiguous in
+// plan order, so these span at most PA_MAXB blocks; the plan checks it).  A
+// step applies z <- P_B(q) with the block factors, forms the workgroup's
+// partial ||q - y_j||^2 of the next q per block it touches, and meets the
+// other workgroups at a grid barrier; every workgroup of block j then sums
+// the block's workgroup partials in the same fixed order, so all of them
+// get the same factor.  The grid is launched only when all its workgroups
+// fit the device at once.  The barrier's wait is bounded: a workgroup that
+// has polled spin_limit times sets a give-up flag that releases every other
+// waiter, all workgroups run to the end, and the host reports the flag.
+struct PaArgs {
+  int steps, G, d, spin_limit;
+  int64_t M;
+  double mu;
+  const float2* v; const float2* ga; const float2* y; const double* U;
+  double2* z;
+  const uint8_t* active;
+  const int32_t* voff; const int32_t* wgb0; const int32_t* gfirst; const int32_t* glast;
+  const double* eps;
+  double2* bfac;
+  double* part;
+  uint32_t* sync;
+};
+
+// sync[0] counts arrivals over the launch (barrier s completes at
+// (s + 1) G), sync[2] is the give-up flag.  Called by one thread of the
+// workgroup, after it has stored the workgroup's partials.  Returns 1 when
+// every workgroup has arrived, 0 after a give-up.
+__device__ int grid_barrier(uint32_t* sync, uint32_t target, int spin_limit) {
+  __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  int polls = 0;
+  while (__hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (__hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return 0;
+    if (++polls > spin_limit) {
+      __hip_atomic_store(&sync[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return 0;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+  (void)__hip_atomic_load(&sync[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  return 1;
+}
+
+__global__ __launch_bounds__(PA_THREADS) void k_alg2_persistent(PaArgs a) {
+  __shared__ double red[PA_THREADS / 64][PA_MAXB];
+  __shared__ double2 fac[PA_MAXB];
+  __shared__ int act[PA_MAXB];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int64_t i0 = int64_t(g) * PA_CHUNK;
+  const int64_t i1 = min(i0 + PA_CHUNK, a.M);
+  const int b0 = a.wgb0[g];
+  int nb = 1;
+  while (nb < PA_MAXB && b0 + nb < a.d && a.voff[b0 + nb] < i1) ++nb;
+  double2 w[PA_PER], z[PA_PER];
+  double U[PA_PER];
+  float2 y[PA_PER];
+  int sl[PA_PER];
+#pragma unroll
+  for (int k = 0; k < PA_PER; ++k) {
+    const int64_t i = i0 + int64_t(k) * PA_THREADS + tid;
+    sl[k] = -1;
+    if (i < i1) {
+      U[k] = a.U[i];
+      w[k] = dual_arg(a.v[i], U[k], a.ga[i]);
+      z[k] = a.z[i];
+      y[k] = a.y[i];
+      int b = 0;
+      while (b + 1 < nb && i >= a.voff[b0 + b + 1]) ++b;
+      sl[k] = b;
+    }
+  }
+  // factors of the first middle step (from the degridding's partials)
+  if (tid < nb) {
+    fac[tid] = a.bfac[b0 + tid];
+    act[tid] = !a.active || a.active[b0 + tid];
+  }
+  __syncthreads();
+  for (int s = 0; s < a.steps; ++s) {
+    double acc[PA_MAXB];
+#pragma unroll
+    for (int b = 0; b < PA_MAXB; ++b) acc[b] = 0.0;
+#pragma unroll
+    for (int k = 0; k < PA_PER; ++k) {
+      if (sl[k] < 0) continue;
+      const int b = sl[k];
+      const double mU = a.mu * U[k];
+      if (act[b]) {
+        const double2 f = fac[b];
+        const double qx = z[k].x - mU * (z[k].x - w[k].x), qy = z[k].y - mU * (z[k].y - w[k].y);
+        z[k].x = f.y != 0.0 ? qx : double(y[k].x) + (qx - double(y[k].x)) * f.x;
+        z[k].y = f.y != 0.0 ? qy : double(y[k].y) + (qy - double(y[k].y)) * f.x;
+      }
+      const double dx = (z[k].x - mU * (z[k].x - w[k].x)) - double(y[k].x);
+      const double dy = (z[k].y - mU * (z[k].y - w[k].y)) - double(y[k].y);
+      const double q2 = dx * dx + dy * dy;
+#pragma unroll
+      for (int bb = 0; bb < PA_MAXB; ++bb) acc[bb] += bb == b ? q2 : 0.0;
+    }
+    // the workgroup's partial per block, summed in a fixed order
+#pragma unroll
+    for (int b = 0; b < PA_MAXB; ++b) {
+      const double t = wave_sum(acc[b]);
+      if (lane == 0) red[wid][b] = t;
+    }
+    __syncthreads();
+    double* part = a.part + size_t(s & 1) * size_t(a.G) * PA_MAXB;
+    if (tid == 0) {
+      for (int b = 0; b < nb; ++b)
+        __hip_atomic_store(&part[size_t(g) * PA_MAXB + b], ((red[0][b] + red[1][b]) + red[2][b]) + red[3][b],
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      (void)grid_barrier(a.sync, uint32_t(s + 1) * uint32_t(a.G), a.spin_limit);
+    }
+    __syncthreads();
+    // the factors of this workgroup's blocks from all their workgroups' partials
+    for (int b = 0; b < nb; ++b) {
+      const int j = b0 + b;
+      double t = 0.0;
+      for (int gg = a.gfirst[j] + tid; gg <= a.glast[j]; gg += PA_THREADS)
+        t += __hip_atomic_load(&part[size_t(gg) * PA_MAXB + (j - a.wgb0[gg])], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      t = wave_sum(t);
+      __syncthreads();   // red is free again
+      if (lane == 0) red[wid][0] = t;
+      __syncthreads();
+      if (tid == 0) {
+        const double r = sqrt(((red[0][0] + red[1][0]) + red[2][0]) + red[3][0]), e = a.eps[j];
+        fac[b] = r > e ? make_double2(e / r, 0.0) : make_double2(1.0, 1.0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < PA_PER; ++k) {
+    const int64_t i = i0 + int64_t(k) * PA_THREADS + tid;
+    if (sl[k] >= 0 && act[sl[k]]) a.z[i] = z[k];
+  }
+  // the last step's factors, for the final projection in the gridding:
+  // stored by the first workgroup of each block (all others hold the same)
+  if (tid < nb && a.gfirst[b0 + tid] == g) a.bfac[b0 + tid] = fac[tid];
+  // the last workgroup out clears the arrival and exit counts for the next launch
+  if (tid == 0) {
+    const uint32_t out = __hip_atomic_fetch_add(&a.sync[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (out == uint32_t(a.G) - 1u) {
+      __hip_atomic_store(&a.sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.sync[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -409,11 +562,11 @@ int alg2_launch(ppd_plan* p, int mode, const double2* w, const float2* v, const 
   int slot;
   PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
   if (p->chunk_max <= 128)
-    hipLaunchKernelGGL(k_alg2<1>, dim3(p->n_launch), dim3(64), 0, p->stream, mode, p->items, p->n_items,
-                       p->segs, w, v, ga, y, U, z, mu, p->bfac, active, part_out);
+    hipLaunchKernelGGL(k_alg2<1>, dim3(p->split1.launch), dim3(64), 0, p->stream, mode, p->items, p->n_items,
+                       p->segs, w, v, ga, y, U, z, mu, p->bfac, active, part_out, p->split1);
   else
-    hipLaunchKernelGGL(k_alg2<4>, dim3(p->n_launch), dim3(256), 0, p->stream, mode, p->items, p->n_items,
-                       p->segs, w, v, ga, y, U, z, mu, p->bfac, active, part_out);
+    hipLaunchKernelGGL(k_alg2<4>, dim3(p->split1.launch), dim3(256), 0, p->stream, mode, p->items, p->n_items,
+                       p->segs, w, v, ga, y, U, z, mu, p->bfac, active, part_out, p->split1);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }
@@ -452,6 +605,46 @@ int secular_solve(ppd_plan* p, const double2* w, const float2* v, const float2* 
   return timer_end(p, slot);
 }
 
+int alg2_persistent_capacity() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_alg2_persistent),
+                                                   PA_THREADS, 0) != hipSuccess)
+    return 0;
+  return cus * per;
+}
+
+int alg2_persistent(ppd_plan* p, const DualArgs& a, int spin_limit) {
+  if (!p->pa_ok) return fail(PPD_EUNSUPPORTED, "persistent Algorithm 2 is not available for this plan");
+  PaArgs pa;
+  pa.steps = a.n_itr - 1;
+  pa.G = p->pa_groups;
+  pa.d = p->d;
+  pa.spin_limit = spin_limit > 0 ? spin_limit : (1 << 20);
+  pa.M = p->M;
+  pa.mu = a.mu;
+  pa.v = a.v;
+  pa.ga = p->gabuf;
+  pa.y = a.y;
+  pa.U = a.U;
+  pa.z = a.z;
+  pa.active = a.active;
+  pa.voff = p->voff_d;
+  pa.wgb0 = p->pa_wgb0;
+  pa.gfirst = p->pa_gfirst;
+  pa.glast = p->pa_glast;
+  pa.eps = p->eps_d;
+  pa.bfac = p->bfac;
+  pa.part = p->pa_part;
+  pa.sync = p->pa_sync;
+  int slot;
+  PPD_TRY(timer_begin(p, KK_SUBITER, &slot));
+  hipLaunchKernelGGL(k_alg2_persistent, dim3(pa.G), dim3(PA_THREADS), 0, p->stream, pa);
+  PPD_HIP(hipGetLastError());
+  return timer_end(p, slot);
+}
+
 int block_factors(ppd_plan* p, const double* part) {
   int slot;
   PPD_TRY(timer_begin(p, KK_MISC, &slot));
@@ -461,7 +654,7 @@ int block_factors(ppd_plan* p, const double* part) {
   return timer_end(p, slot);
 }
 
-// Unfused reference form of steps 10-11: per block, per sub-iteration,
+// Unfused reference form of the data-dual update: per block, per sub-iteration,
 // separate FP64 launches.  Expects Theta G F Z x~ in p->ybuf (plan order).
 int plain_dual(ppd_plan* p, const DualArgs& a) {
   for (int j = 0; j < p->d; ++j) {

@@ -226,7 +226,7 @@ __device__ inline double block_sum(double v, double* red) {
 // Inverse rows: half rows -> image rows.  PRIMAL fuses Algorithm 3 steps
 // 28-30 and the FP64 statistics partials of the new iterate; NEXT also runs
 // the forward row pass of the new x~ (the first transform of the next
-// iteration's step 4) on the rows just updated, into half_next.
+// iteration's F Z x~) on the rows just updated, into half_next.
 template <bool PRIMAL, bool NEXT>
 __global__ void k_fft_rows_inv(const float2* __restrict__ half, const float2* __restrict__ tw,
                                const float* __restrict__ dpx, const float* __restrict__ dpy,
@@ -272,12 +272,12 @@ __global__ void k_fft_rows_inv(const float2* __restrict__ half, const float2* __
       x[idx] = val;
     } else {
       const double xo = x[idx];
-      double xb = xo - tau * (eta * double(val) + zeta * double(ut[idx]));   // step 28
+      double xb = xo - tau * (eta * double(val) + zeta * double(ut[idx]));   // primal step, then P_C
       xb = xb > 0.0 ? xb : 0.0;
-      const double xn = xo + lambda * (xb - xo);                              // step 29
+      const double xn = xo + lambda * (xb - xo);                              // relaxation
       const float xnf = float(xn);
       x[idx] = xnf;
-      const float xtf = float(2.0 * xb - xo);                                 // step 30
+      const float xtf = float(2.0 * xb - xo);                                 // x~ = 2 xbar - x
       xt[idx] = xtf;
       if (NEXT) xtn[k] = xtf;
       const double dn = double(xnf) - xo;

@@ -70,7 +70,8 @@ __global__ __launch_bounds__(256) void k_stats(const double* __restrict__ ppart,
     for (int k = 0; k < 4; ++k) s[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
     double rmax = 0.0;
     for (int j = 0; j < d; ++j) rmax = fmax(rmax, out[8 + j] / eps[j]);
-    out[0] = sqrt(s[0] / s[1]);
+    // ||x_t - x_{t-1}|| / ||x_t||, 0 when both vanish (an all-zero iterate)
+    out[0] = sqrt(s[0]) / fmax(sqrt(s[1]), 1e-300);
     out[1] = sqrt(s[1]);
     out[2] = has_truth ? 20.0 * log10(sqrt(s[3] / s[2])) : __builtin_nan("");
     out[3] = rmax;
@@ -150,6 +151,8 @@ struct IterCtx {
   int prox, n_newton;
   const uint8_t* basis_active;
   bool sara_forked;   // SARA on the second stream (eager), else the data path (graph)
+  bool persistent;    // Algorithm 2 middle steps in one persistent launch
+  int spin_limit;     // its grid-barrier bound (0: default)
 };
 
 // Runs the plan's launches on another stream for the lifetime of the object.
@@ -160,41 +163,50 @@ struct OnStream {
   ~OnStream() { p->stream = saved; }
 };
 
-// The data-fidelity path of one iteration (steps 4-12 and the inverse
-// column FFT of step 28) on the plan's current stream.
+// The data-fidelity path of one iteration (F Z x~, the data-dual update
+// of every block and the gridding, then the inverse column FFT of the
+// primal step) on the plan's current stream.
 int data_path(ppd_plan* p, const IterCtx& c) {
-  PPD_TRY(fft_cols_forward(p, p->half_f));                  // step 4: a = F Z x~ (rows done)
+  PPD_TRY(fft_cols_forward(p, p->half_f));                  // a = F Z x~ (rows done)
   if (c.form == PPD_FORM_FUSED && c.prox == PPD_PROX_EXACT) {
-    PPD_TRY(degrid_dual(p, c.dual, nullptr));               // step 10 argument w (no Algorithm 2 partials)
+    PPD_TRY(degrid_dual(p, c.dual, nullptr));               // dual argument w (no Algorithm 2 partials)
     PPD_TRY(secular_solve(p, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.n_newton));  // prox^U_h(w)
-    PPD_TRY(grid_dual_exact(p, c.dual));                    // steps 10-12
+    PPD_TRY(grid_dual_exact(p, c.dual));                    // dual finish, relaxation, gridding
   } else if (c.form == PPD_FORM_FUSED) {
     double* pa = p->part;
     double* pb = p->part + p->n_segs;
-    PPD_TRY(degrid_dual(p, c.dual, pa));                    // step 10 argument, first Alg. 2 step
-    for (int s = 1; s < c.dual.n_itr; ++s) {
-      PPD_TRY(alg2_launch(p, 1, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb,
-                          c.dual.active));
-      std::swap(pa, pb);
+    PPD_TRY(degrid_dual(p, c.dual, pa));                    // dual argument, first Alg. 2 step
+    if (c.dual.n_itr > 1 && c.persistent) {
+      // the middle steps in one launch, state in registers; it leaves the
+      // last step's factors for the gridding
+      PPD_TRY(block_factors(p, pa));
+      PPD_TRY(alg2_persistent(p, c.dual, c.spin_limit));
+      PPD_TRY(grid_dual_factored(p, c.dual));               // last projection, dual finish, gridding
+    } else {
+      for (int s = 1; s < c.dual.n_itr; ++s) {
+        PPD_TRY(alg2_launch(p, 1, nullptr, c.dual.v, p->gabuf, c.dual.y, c.dual.U, c.dual.z, c.dual.mu, pa, pb,
+                            c.dual.active));
+        std::swap(pa, pb);
+      }
+      PPD_TRY(grid_dual(p, c.dual, pa));                    // last projection, dual finish, gridding
     }
-    PPD_TRY(grid_dual(p, c.dual, pa));                      // steps 10-12
   } else {
     PPD_TRY(degrid_plain(p, p->ybuf));
-    PPD_TRY(plain_dual(p, c.dual));                         // steps 10-11, block by block
-    PPD_TRY(grid_plain(p, c.dual.v));                       // step 12
+    PPD_TRY(plain_dual(p, c.dual));                         // data-dual update, block by block
+    PPD_TRY(grid_plain(p, c.dual.v));                       // G^H Theta^H v
   }
   return fft_cols_inverse(p);
 }
 
-// Steps 19-21 (SARA dual update and synthesis) on the plan's current stream.
+// The sparsity dual update and synthesis (SARA) on the plan's current stream.
 int sara_path(ppd_plan* p, const IterCtx& c) {
-  PPD_TRY(sara_dual(p, c.primal.xt, c.u, c.alpha, c.lambda, c.W, c.basis_active));   // steps 19-20
-  return sara_synthesis(p, c.u, p->ut, c.W);                // step 21, summed over i
+  PPD_TRY(sara_dual(p, c.primal.xt, c.u, c.alpha, c.lambda, c.W, c.basis_active));   // clip and relaxation
+  return sara_synthesis(p, c.u, p->ut, c.W);                // Psi u, summed over the bases
 }
 
 // One iteration of Algorithm 3 on the plan's stream.  SARA needs only x~
 // and u, so it runs concurrently with the data-fidelity path, one of the two
-// forked to the plan's second stream; the primal update (steps 28-30) waits
+// forked to the plan's second stream; the primal update waits
 // for both on the plan's stream.  Eager, SARA is forked and the data path
 // stays on the plan's stream (no queue hand-off at its start); captured
 // into a graph, the data path is forked: replayed graphs put a forked SARA
@@ -219,20 +231,48 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
     PPD_TRY(sara_path(p, c));
   }
   PPD_HIP(hipStreamWaitEvent(p->stream, p->ev_join, 0));
-  // steps 28-30, and the forward row pass of the new x~ for the next step 4
+  // the primal update, and the forward row pass of the new x~ for the next iteration
   return fft_rows_inverse_primal(p, c.primal, p->half_f);
 }
 
 std::string graph_key(const IterCtx& c) {
-  char buf[512];
-  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d %d %d",
+  char buf[600];
+  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d %d %d %d %d",
                 (void*)c.dual.y, (void*)c.dual.U, (void*)c.dual.v, (void*)c.dual.z, (void*)c.primal.x,
                 (void*)c.primal.xt, (void*)c.primal.x_true, (void*)c.u, (void*)c.primal.ut, (void*)c.W,
                 (const void*)c.dual.active, (const void*)c.basis_active, (const void*)c.primal.part, (const void*)c.dual.rpart,
                 c.dual.mu,
                 c.dual.lambda, c.primal.tau, c.primal.eta, c.primal.zeta, double(c.alpha),
-                double(c.lambda), c.dual.n_itr, c.form, c.prox, c.n_newton);
+                double(c.lambda), c.dual.n_itr, c.form, c.prox, c.n_newton, int(c.persistent), c.spin_limit);
   return std::string(buf);
+}
+
+// The instantiated graph of one iteration with context c in graph slot
+// `slot` (captured on first use, re-captured when a pointer or scalar of c
+// changes).
+int iteration_graph(ppd_plan* p, const IterCtx& c, int slot, hipGraphExec_t* out) {
+  const std::string key = graph_key(c);
+  if (!p->graph_exec[slot] || key != p->graph_key[slot]) {
+    if (p->graph_exec[slot]) (void)hipGraphExecDestroy(p->graph_exec[slot]);
+    if (p->graph[slot]) (void)hipGraphDestroy(p->graph[slot]);
+    p->graph_exec[slot] = nullptr;
+    p->graph[slot] = nullptr;
+    p->graph_key[slot].clear();
+    PPD_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    const int cst = one_iteration(p, c);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->stream, &g);
+    if (cst != PPD_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return cst;
+    }
+    if (e != hipSuccess) return fail(PPD_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    p->graph[slot] = g;
+    PPD_HIP(hipGraphInstantiate(&p->graph_exec[slot], g, nullptr, nullptr, 0));
+    p->graph_key[slot] = key;
+  }
+  *out = p->graph_exec[slot];
+  return PPD_OK;
 }
 
 }  // namespace
@@ -316,34 +356,28 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   c.basis_active = prm->basis_active;
   c.n_newton = prm->n_newton == 0 ? 12 : prm->n_newton;
   c.sara_forked = !prm->use_graph;
+  if (prm->persistent != PPD_PERSIST_AUTO && prm->persistent != PPD_PERSIST_OFF)
+    return fail(PPD_EINVAL, "ppd_iterate: unknown persistent mode");
+  if (prm->spin_limit < 0) return fail(PPD_EINVAL, "ppd_iterate: spin_limit must be >= 0");
+  c.persistent = prm->persistent == PPD_PERSIST_AUTO && p->pa_ok && prm->form == PPD_FORM_FUSED &&
+                 prm->prox == PPD_PROX_FB && prm->n_itr > 1;
+  c.spin_limit = prm->spin_limit;
 
   if (n_iter > 0) {
     // the first iteration's forward row pass; each iteration then leaves
     // the next one's
     PPD_TRY(fft_rows_forward(p, st->xt, p->half_f));
     if (prm->use_graph) {
-      const std::string key = graph_key(c);
-      if (!p->graph_exec || key != p->graph_key) {
-        if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
-        if (p->graph) (void)hipGraphDestroy(p->graph);
-        p->graph_exec = nullptr;
-        p->graph = nullptr;
-        p->graph_key.clear();
-        PPD_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-        const int cst = one_iteration(p, c);
-        hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(p->stream, &g);
-        if (cst != PPD_OK) {
-          if (g) (void)hipGraphDestroy(g);
-          return cst;
-        }
-        if (e != hipSuccess) return fail(PPD_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-        p->graph = g;
-        PPD_HIP(hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0));
-        p->graph_key = key;
-      }
+      // two captured iterations: slot 1 forms the statistics partials (the
+      // iterations whose statistics are reduced), slot 0 does not
+      IterCtx c0 = c;
+      c0.primal.part = nullptr;
+      c0.dual.rpart = nullptr;
       for (int t = 0; t < n_iter; ++t) {
-        PPD_HIP(hipGraphLaunch(p->graph_exec, p->stream));
+        const bool read = (t + 1 == n_iter && (stats || residual)) || (every > 0 && (t + 1) % every == 0);
+        hipGraphExec_t ex = nullptr;
+        PPD_TRY(iteration_graph(p, read ? c : c0, read && c.primal.part ? 1 : 0, &ex));
+        PPD_HIP(hipGraphLaunch(ex, p->stream));
         PPD_TRY(periodic(t + 1));
       }
     } else {
@@ -364,8 +398,18 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
     if (n_iter == 0) return fail(PPD_EINVAL, "ppd_iterate: statistics need n_iter >= 1");
     PPD_TRY(stats_finalize(p, prm->x_true != nullptr, prm->form == PPD_FORM_PLAIN, p->stats_d));
     std::vector<double> h(8 + p->d);
+    uint32_t gave_up = 0;
     PPD_HIP(hipMemcpyAsync(h.data(), p->stats_d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, p->stream));
+    PPD_HIP(hipMemcpyAsync(&gave_up, p->pa_sync + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, p->stream));
     PPD_HIP(hipStreamSynchronize(p->stream));
+    if (gave_up) {
+      // a grid barrier of the persistent launch gave up waiting (this call
+      // or an earlier one without statistics): its results are not valid
+      PPD_HIP(hipMemsetAsync(p->pa_sync + 2, 0, sizeof(uint32_t), p->stream));
+      PPD_HIP(hipStreamSynchronize(p->stream));
+      return fail(PPD_EDEVICE, "ppd_iterate: a grid barrier of the persistent Algorithm 2 launch gave up "
+                               "waiting; the iterates of this call are not valid");
+    }
     if (stats) {
       stats->iter = st->iter;
       stats->rel_change = h[0];
@@ -375,7 +419,7 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
     }
     if (residual)
       for (int j = 0; j < p->d; ++j) residual[j] = h[8 + j];
-    if (!std::isfinite(h[1]) || !std::isfinite(h[3]) || (prm->x_true && std::isnan(h[2])))
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[3]) || (prm->x_true && std::isnan(h[2])))
       return fail(PPD_ENONFINITE, "ppd_iterate: non-finite statistics");
   }
   return PPD_OK;

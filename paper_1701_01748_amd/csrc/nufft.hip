@@ -134,15 +134,15 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
     float2* __restrict__ out, const float2* __restrict__ y, const double* __restrict__ U,
     const float2* __restrict__ v, const double2* __restrict__ z, float2* __restrict__ gout, double mu,
-    double* __restrict__ part, double* __restrict__ rpart) {
+    double* __restrict__ part, double* __restrict__ rpart, XcdSplit xs) {
   constexpr int R = T + 7;
   constexpr int NW = DegridCfg<T>::NW;
   constexpr bool B128 = PPD_DEGRID_B128 && T == 8;
   __shared__ __align__(16) float2 reg[B128 ? 2 * G8_COPY : R * R];
   __shared__ ItemTab tab;
   __shared__ double s_q[NW][MAX_ITEM_SEGS], s_r[NW][MAX_ITEM_SEGS];
-  const int ii = xcd_remap(blockIdx.x, gridDim.x);
-  if (ii >= n_items) return;
+  const int ii = xcd_unit(blockIdx.x, xs);
+  if (ii < 0 || ii >= n_items) return;
   const Item it = items[ii];
   const int r0 = it.ty * T, c0 = it.tx * T;
   const int lane = threadIdx.x & 63;
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(64 * DegridCfg<T>::NW) void k_degrid(
       if (!DUAL) {
         out[pi] = g;
       } else {
-        // Algorithm 3 step 10: w = U^-1 v + Theta G a (Theta G a kept for the
+        // argument of the data-dual update of Algorithm 3: w = U^-1 v + Theta G a (Theta G a kept for the
         // gridding pass, which rebuilds w); first Algorithm 2 step
         gout[pi] = g;
         const double2 we = dual_arg(ve, Ue, g);
@@ -335,14 +335,14 @@ __device__ __forceinline__ void grid_load(const GridSrc& g, const ItemTab& tab, 
 
 // The value a visibility spreads onto the grid (before Theta).  In the dual
 // mode: the last Algorithm 2 projection z = P_B(q) with the block's factor
-// (or the exact prox with the block's nu), then steps 10-11; an inactive
-// block (randomised updates, steps 14-17) keeps v and z and spreads its v.
+// (or the exact prox with the block's nu), then the dual finish and relaxation; an inactive
+// block (randomised updates of Algorithm 3) keeps v and z and spreads its v.
 template <bool DUAL>
 __device__ __forceinline__ float2 grid_value(const GridBatch& bt, double mu, double lambda, int exact,
                                              double2& znew, float2& vnew) {
   if (!DUAL) return bt.vin;
   if (!bt.act) return bt.v;
-  const double2 bw = dual_arg(bt.v, bt.U, bt.ga);   // w of step 10
+  const double2 bw = dual_arg(bt.v, bt.U, bt.ga);   // w of the data-dual update
   double zx, zy;
   if (exact) {
     // exact prox: (U w + nu y) / (U + nu) with the block's nu, w if nu = 0
@@ -391,7 +391,8 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
     const float2* __restrict__ vin, const float2* __restrict__ y, const double* __restrict__ U,
     float2* __restrict__ v, double2* __restrict__ z, const float2* __restrict__ ga, double mu,
-    double lambda, const double2* __restrict__ bfac, int exact, const uint8_t* __restrict__ active) {
+    double lambda, const double2* __restrict__ bfac, int exact, const uint8_t* __restrict__ active,
+    XcdSplit xs) {
   constexpr int R = GridCfg<T>::R;
   constexpr int RS = GridCfg<T>::RS;
   constexpr int C = GridCfg<T>::C;
@@ -401,8 +402,8 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
   __shared__ float2 wxv[NW][64 * WXS];         // wx[b] * value, per visibility of the batch
   __shared__ float wyb[NW][64 * WXS];          // wy[a]
   __shared__ ItemTab tab;
-  const int ii = xcd_remap(blockIdx.x, gridDim.x);
-  if (ii >= n_items) return;
+  const int ii = xcd_unit(blockIdx.x, xs);
+  if (ii < 0 || ii >= n_items) return;
   const Item it = items[ii];
   const int r0 = it.ty * T, c0 = it.tx * T;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -525,12 +526,6 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
 // item's first batch, are loaded before the current step is prepared and
 // applied, and the next item's segment list is fetched into registers when
 // the current item starts.  Only the first step of a run waits for memory.
-#ifndef PPD_GRIDM_RUN
-#define PPD_GRIDM_RUN 2
-#endif
-#ifndef PPD_GRIDM_WPG
-#define PPD_GRIDM_WPG 1
-#endif
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int GM_T = 8;
 constexpr int GM_AS = 17;   // A row stride (floats): spreads the prepare writes over banks
@@ -564,22 +559,21 @@ __device__ __forceinline__ void tab_from_seg(const Seg& sg, int lane, ItemTab& t
 // The next item's region and segment list are loaded into registers while
 // the current item is worked on; per-segment sums are kept by the lane of
 // the segment (same order as k_degrid's).
-#ifndef PPD_DEGRID_RUN
-#define PPD_DEGRID_RUN 2
-#endif
 __global__ __launch_bounds__(64) void k_degrid8(
     const float2* __restrict__ grid, int Kx, int Ky, const Item* __restrict__ items, int n_items,
     const Seg* __restrict__ segs, const float* __restrict__ wu, const float* __restrict__ wv,
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
     const float2* __restrict__ y, const double* __restrict__ U,
     const float2* __restrict__ v, const double2* __restrict__ z, float2* __restrict__ gout, double mu,
-    double* __restrict__ part, double* __restrict__ rpart) {
+    double* __restrict__ part, double* __restrict__ rpart, XcdSplit xs) {
   constexpr int T = 8, R = T + 7, RUN = PPD_DEGRID_RUN > 0 ? PPD_DEGRID_RUN : 1;
   constexpr int RPT = (R * R + 63) / 64;
   static_assert(RUN <= 64, "a run's items are held one per lane");
   __shared__ float2 reg[R * R];
   __shared__ ItemTab tab;
-  const int i0 = xcd_remap(blockIdx.x, gridDim.x) * RUN;
+  const int unit = xcd_unit(blockIdx.x, xs);
+  if (unit < 0) return;
+  const int i0 = unit * RUN;
   if (i0 >= n_items) return;
   const int i1 = min(i0 + RUN, n_items);
   const int lane = threadIdx.x;
@@ -673,7 +667,7 @@ __global__ __launch_bounds__(64) void k_degrid8(
           ax = fmaf(wya, sx, ax);
           ay = fmaf(wya, sy, ay);
         }
-        // Algorithm 3 step 10 argument and the first Algorithm 2 step, as in
+        // the data-dual argument of Algorithm 3 and the first Algorithm 2 step, as in
         // k_degrid
         const float2 g = make_float2(ax * cb.th, ay * cb.th);
         gout[pi] = g;
@@ -711,7 +705,8 @@ __global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
     const float* __restrict__ theta, double su, double sv, const float* __restrict__ kbc,
     const float2* __restrict__ vin, const float2* __restrict__ y, const double* __restrict__ U,
     float2* __restrict__ v, double2* __restrict__ z, const float2* __restrict__ ga, double mu,
-    double lambda, const double2* __restrict__ bfac, int exact, const uint8_t* __restrict__ active) {
+    double lambda, const double2* __restrict__ bfac, int exact, const uint8_t* __restrict__ active,
+    XcdSplit xs) {
   constexpr int T = GM_T, R = T + 7, WPG = PPD_GRIDM_WPG;
   static_assert(R <= 16, "the region must fit one 16 x 16 product tile");
   __shared__ float sAw[WPG][32 * GM_AS];
@@ -722,7 +717,9 @@ __global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
   __syncthreads();
   // each wave of the workgroup works alone from here on
   const int wid = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
-  const int i0 = (xcd_remap(blockIdx.x, gridDim.x) * WPG + wid) * PPD_GRIDM_RUN;
+  const int unit = xcd_unit(blockIdx.x, xs);
+  if (unit < 0) return;
+  const int i0 = (unit * WPG + wid) * PPD_GRIDM_RUN;
   if (i0 >= n_items) return;
   const int i1 = min(i0 + PPD_GRIDM_RUN, n_items);
   const int lane = threadIdx.x & 63;
@@ -965,58 +962,44 @@ __global__ void k_permute(const int32_t* __restrict__ perm, int64_t M, int to_us
   }
 }
 
-// workgroups of the 8 x 8 degridding in runs: a multiple of the XCD count
-int degrid8_launch(const ppd_plan* p) {
-  constexpr int run = PPD_DEGRID_RUN > 0 ? PPD_DEGRID_RUN : 1;
-  const int wgs = (p->n_items + run - 1) / run;
-  return ((wgs + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
-}
 
 template <int T>
 int launch_degrid(ppd_plan* p, bool dual, float2* out, const DualArgs* a, double* part_out) {
   // runs for the fused dual pass only: plain Phi is faster one item per
   // workgroup (27.4 against 29.7 us at 512^2, M = 1.3M)
   if (T == 8 && PPD_DEGRID_RUN > 0 && dual) {
-    hipLaunchKernelGGL(k_degrid8, dim3(degrid8_launch(p)), dim3(64), 0, p->stream, p->grid_f, p->Kx, p->Ky,
+    hipLaunchKernelGGL(k_degrid8, dim3(p->split_degrid.launch), dim3(64), 0, p->stream, p->grid_f, p->Kx, p->Ky,
                        p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale, p->sv_scale, p->kbc,
-                       a->y, a->U, a->v, a->z, p->gabuf, a->mu, part_out, a->rpart);
+                       a->y, a->U, a->v, a->z, p->gabuf, a->mu, part_out, a->rpart, p->split_degrid);
     PPD_HIP(hipGetLastError());
     return PPD_OK;
   }
   if (!dual) {
-    hipLaunchKernelGGL((k_degrid<T, false>), dim3(p->n_launch), dim3(64 * DegridCfg<T>::NW), 0, p->stream, p->grid_f,
-                       p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
+    hipLaunchKernelGGL((k_degrid<T, false>), dim3(p->split1.launch), dim3(64 * DegridCfg<T>::NW), 0, p->stream,
+                       p->grid_f, p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, out, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0,
-                       nullptr, nullptr);
+                       nullptr, nullptr, p->split1);
   } else {
-    hipLaunchKernelGGL((k_degrid<T, true>), dim3(p->n_launch), dim3(64 * DegridCfg<T>::NW), 0, p->stream, p->grid_f,
-                       p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
+    hipLaunchKernelGGL((k_degrid<T, true>), dim3(p->split1.launch), dim3(64 * DegridCfg<T>::NW), 0, p->stream,
+                       p->grid_f, p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->gabuf, a->mu,
-                       part_out, a->rpart);
+                       part_out, a->rpart, p->split1);
   }
   PPD_HIP(hipGetLastError());
   return PPD_OK;
 }
 
-// workgroups of the product gridding: one wave per run of items, a multiple
-// of the XCD count
-int gridm_launch(const ppd_plan* p) {
-  const int runs = (p->n_items + PPD_GRIDM_RUN - 1) / PPD_GRIDM_RUN;
-  const int wgs = (runs + PPD_GRIDM_WPG - 1) / PPD_GRIDM_WPG;
-  return ((wgs + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
-}
-
 int launch_grid_mfma(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, int exact) {
   if (!dual) {
-    hipLaunchKernelGGL((k_grid_mfma<false>), dim3(gridm_launch(p)), dim3(64 * PPD_GRIDM_WPG), 0, p->stream,
+    hipLaunchKernelGGL((k_grid_mfma<false>), dim3(p->split_grid.launch), dim3(64 * PPD_GRIDM_WPG), 0, p->stream,
                        p->gscratch, p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta,
                        p->su_scale, p->sv_scale, p->kbc, vin, nullptr, nullptr, nullptr, nullptr, nullptr,
-                       0.0, 0.0, nullptr, 0, nullptr);
+                       0.0, 0.0, nullptr, 0, nullptr, p->split_grid);
   } else {
-    hipLaunchKernelGGL((k_grid_mfma<true>), dim3(gridm_launch(p)), dim3(64 * PPD_GRIDM_WPG), 0, p->stream,
+    hipLaunchKernelGGL((k_grid_mfma<true>), dim3(p->split_grid.launch), dim3(64 * PPD_GRIDM_WPG), 0, p->stream,
                        p->gscratch, p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta,
                        p->su_scale, p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->gabuf, a->mu,
-                       a->lambda, p->bfac, exact, a->active);
+                       a->lambda, p->bfac, exact, a->active, p->split_grid);
   }
   PPD_HIP(hipGetLastError());
   return PPD_OK;
@@ -1025,15 +1008,15 @@ int launch_grid_mfma(ppd_plan* p, bool dual, const float2* vin, const DualArgs* 
 template <int T>
 int launch_grid(ppd_plan* p, bool dual, const float2* vin, const DualArgs* a, int exact) {
   if (!dual) {
-    hipLaunchKernelGGL((k_grid<T, false>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
-                       p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
+    hipLaunchKernelGGL((k_grid<T, false>), dim3(p->split1.launch), dim3(GridCfg<T>::THREADS), 0, p->stream,
+                       p->gscratch, p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, vin, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0,
-                       0.0, nullptr, 0, nullptr);
+                       0.0, nullptr, 0, nullptr, p->split1);
   } else {
-    hipLaunchKernelGGL((k_grid<T, true>), dim3(p->n_launch), dim3(GridCfg<T>::THREADS), 0, p->stream, p->gscratch,
-                       p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
+    hipLaunchKernelGGL((k_grid<T, true>), dim3(p->split1.launch), dim3(GridCfg<T>::THREADS), 0, p->stream,
+                       p->gscratch, p->Kx, p->Ky, p->items, p->n_items, p->segs, p->wu, p->wv, p->theta, p->su_scale,
                        p->sv_scale, p->kbc, nullptr, a->y, a->U, a->v, a->z, p->gabuf, a->mu,
-                       a->lambda, p->bfac, exact, a->active);
+                       a->lambda, p->bfac, exact, a->active, p->split1);
   }
   PPD_HIP(hipGetLastError());
   return PPD_OK;
@@ -1098,6 +1081,11 @@ int grid_plain(ppd_plan* p, const float2* v) {
 
 int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in) {
   PPD_TRY(block_factors(p, part_in));
+  PPD_TRY(dispatch_grid(p, true, nullptr, &a, 0));
+  return fold_grid(p);
+}
+
+int grid_dual_factored(ppd_plan* p, const DualArgs& a) {
   PPD_TRY(dispatch_grid(p, true, nullptr, &a, 0));
   return fold_grid(p);
 }

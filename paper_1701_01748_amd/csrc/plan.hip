@@ -214,8 +214,10 @@ static int dalloc(ppd_plan* p, T** ptr, size_t count) {
 static void destroy_plan(ppd_plan* p) {
   if (!p) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
-  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (int k = 0; k < 2; ++k) {
+    if (p->graph_exec[k]) (void)hipGraphExecDestroy(p->graph_exec[k]);
+    if (p->graph[k]) (void)hipGraphDestroy(p->graph[k]);
+  }
   if (p->aux) (void)hipStreamSynchronize(p->aux);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
@@ -438,7 +440,42 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   p->n_items = int(items.size());
   p->n_segs = int(segs.size());
   p->n_tiles = ntiles;
-  p->n_launch = ((p->n_items + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
+  // work-balanced XCD bands of the item launches: the cost of an item is
+  // its 64-point batches plus one for staging and storing its region
+  {
+    std::vector<double> cost(p->n_items);
+    for (int i = 0; i < p->n_items; ++i) {
+      int64_t c = 0;
+      for (int g = items[i].seg0; g < items[i].seg1; ++g) c += segs[g].count;
+      cost[i] = double((c + 63) / 64) + 1.0;
+    }
+    auto split = [&](int unit) {
+      XcdSplit sp{};
+      sp.unit = unit;
+      const int nu = (p->n_items + unit - 1) / unit;
+      std::vector<double> pre(nu + 1, 0.0);
+      for (int u = 0; u < nu; ++u) {
+        double c = 0.0;
+        for (int i = u * unit; i < std::min(p->n_items, (u + 1) * unit); ++i) c += cost[i];
+        pre[u + 1] = pre[u] + c;
+      }
+      sp.off[0] = 0;
+      sp.off[MAX_XCD] = nu;
+      int u = 0;
+      for (int k = 1; k < MAX_XCD; ++k) {
+        const double target = pre[nu] * k / MAX_XCD;
+        while (u < nu && pre[u] < target) ++u;
+        sp.off[k] = u;
+      }
+      int longest = 0;
+      for (int k = 0; k < MAX_XCD; ++k) longest = std::max(longest, sp.off[k + 1] - sp.off[k]);
+      sp.launch = std::max(1, longest) * MAX_XCD;
+      return sp;
+    };
+    p->split1 = split(1);
+    p->split_degrid = split(PPD_DEGRID_RUN > 0 ? PPD_DEGRID_RUN : 1);
+    p->split_grid = split(PPD_GRIDM_RUN * PPD_GRIDM_WPG);
+  }
   p->n_tile_launch = ((ntiles + MAX_XCD - 1) / MAX_XCD) * MAX_XCD;
   p->items_host = items;
   p->segs_host = segs;
@@ -502,6 +539,29 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   cstart.push_back(int32_t(M));
   p->n_sec_chunks = int(cblock.size());
 
+  // persistent Algorithm 2: workgroup g owns plan-order points
+  // [g PA_CHUNK, (g+1) PA_CHUNK); its first block, and each block's range of
+  // workgroups (blocks are contiguous in plan order)
+  p->pa_groups = int((M + PA_CHUNK - 1) / PA_CHUNK);
+  std::vector<int32_t> wgb0(p->pa_groups), gfirst(p->d), glast(p->d), voff(p->d + 1);
+  bool pa_fits = true;
+  {
+    int j = 0;
+    for (int g = 0; g < p->pa_groups; ++g) {
+      const int64_t a0 = int64_t(g) * PA_CHUNK, a1 = std::min<int64_t>(a0 + PA_CHUNK, M);
+      while (p->block_off[j + 1] <= a0) ++j;
+      wgb0[g] = j;
+      int nb = 1;
+      while (j + nb < p->d && p->block_off[j + nb] < a1) ++nb;
+      if (nb > PA_MAXB) pa_fits = false;
+    }
+    for (int jj = 0; jj < p->d; ++jj) {
+      gfirst[jj] = int32_t(p->block_off[jj] / PA_CHUNK);
+      glast[jj] = int32_t((p->block_off[jj + 1] - 1) / PA_CHUNK);
+    }
+    for (int jj = 0; jj <= p->d; ++jj) voff[jj] = int32_t(p->block_off[jj]);
+  }
+
   // ---- device memory -----------------------------------------------------------
   const size_t K2 = size_t(p->Kx) * p->Ky;
   const size_t N = size_t(p->nx) * p->ny;
@@ -540,6 +600,12 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   A(dalloc(p, &p->sec_coff, coff.size()));
   A(dalloc(p, &p->sec_part, 4 * cblock.size()));
   A(dalloc(p, &p->sec_nu, 2 * size_t(p->d)));
+  A(dalloc(p, &p->voff_d, p->d + 1));
+  A(dalloc(p, &p->pa_wgb0, p->pa_groups));
+  A(dalloc(p, &p->pa_gfirst, p->d));
+  A(dalloc(p, &p->pa_glast, p->d));
+  A(dalloc(p, &p->pa_part, 2 * size_t(p->pa_groups) * PA_MAXB));
+  A(dalloc(p, &p->pa_sync, 4));
   A(dalloc(p, &p->part, 2 * size_t(p->n_segs)));
   A(dalloc(p, &p->rpart, p->n_segs));
   A(dalloc(p, &p->eps_d, p->d));
@@ -594,6 +660,18 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   up(p->twx, twx.data(), sizeof(float2) * twx.size());
   up(p->twy, twy.data(), sizeof(float2) * twy.size());
   up(p->filt, filt.data(), 4 * filt.size());
+  up(p->voff_d, voff.data(), 4 * voff.size());
+  up(p->pa_wgb0, wgb0.data(), 4 * wgb0.size());
+  up(p->pa_gfirst, gfirst.data(), 4 * gfirst.size());
+  up(p->pa_glast, glast.data(), 4 * glast.size());
+  {
+    const uint32_t zeros[4] = {0u, 0u, 0u, 0u};
+    up(p->pa_sync, zeros, sizeof(zeros));
+  }
+  // the persistent launch needs all its workgroups on the device at once
+  if (st == PPD_OK) {
+    p->pa_ok = pa_fits && p->pa_groups <= alg2_persistent_capacity();
+  }
   // default priority on purpose: both streams of an iteration are equal
   if (st == PPD_OK && (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
                        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -637,15 +715,13 @@ int ppd_plan_destroy(ppd_plan* plan) {
 
 int ppd_plan_set_stream(ppd_plan* plan, void* stream) {
   if (!plan) return fail(PPD_EINVAL, "NULL plan");
-  if (plan->graph_exec) {
-    (void)hipGraphExecDestroy(plan->graph_exec);
-    plan->graph_exec = nullptr;
+  for (int k = 0; k < 2; ++k) {
+    if (plan->graph_exec[k]) (void)hipGraphExecDestroy(plan->graph_exec[k]);
+    if (plan->graph[k]) (void)hipGraphDestroy(plan->graph[k]);
+    plan->graph_exec[k] = nullptr;
+    plan->graph[k] = nullptr;
+    plan->graph_key[k].clear();
   }
-  if (plan->graph) {
-    (void)hipGraphDestroy(plan->graph);
-    plan->graph = nullptr;
-  }
-  plan->graph_key.clear();
   plan->stream = static_cast<hipStream_t>(stream);
   return PPD_OK;
 }
@@ -664,6 +740,8 @@ int ppd_plan_get_info(const ppd_plan* p, ppd_plan_info* info) {
   info->n_chunks = p->n_items;
   info->kb_beta = p->beta;
   info->device_bytes = p->device_bytes;
+  info->persistent = p->pa_ok ? 1 : 0;
+  info->pad_ = 0;
   return PPD_OK;
 }
 

@@ -37,10 +37,37 @@ constexpr int FILT_STRIDE = 16;   // max Daubechies taps (db8)
 constexpr int SEC_CHUNK = 2048;   // points per workgroup of an exact-prox Newton pass
 constexpr int MAX_ITEM_SEGS = 64; // per-block segments of one work item (one wave scans them)
 constexpr int MAX_XCD = 8;
+constexpr int PA_THREADS = 256;   // persistent Algorithm 2: threads per workgroup
+constexpr int PA_PER = 8;         // points per thread held in registers
+constexpr int PA_CHUNK = PA_THREADS * PA_PER;
+constexpr int PA_MAXB = 4;        // data blocks one workgroup's points may span
 #ifndef PPD_FOLD_HEAVY
 #define PPD_FOLD_HEAVY 16
 #endif
 constexpr int FOLD_HEAVY = PPD_FOLD_HEAVY;   // item regions above which a tile's fold takes a whole workgroup
+// Work items per workgroup of the 8 x 8 degridding with the dual update and
+// of the matrix-core gridding (runs of consecutive items, one wave each).
+#ifndef PPD_DEGRID_RUN
+#define PPD_DEGRID_RUN 2
+#endif
+#ifndef PPD_GRIDM_RUN
+#define PPD_GRIDM_RUN 2
+#endif
+#ifndef PPD_GRIDM_WPG
+#define PPD_GRIDM_WPG 1
+#endif
+
+// Launch order of the work items over the XCDs: the items, in spatial
+// order, are cut into 8 contiguous bands of near-equal work (64-point
+// batches plus one per item for its region), XCD k taking the units
+// (workgroups of `unit` consecutive items) [off[k], off[k+1]).  Workgroup
+// ids go round-robin over the XCDs, so workgroup b runs unit
+// off[b mod 8] + b / 8 of band b mod 8, if that band has it.
+struct XcdSplit {
+  int32_t off[MAX_XCD + 1];
+  int32_t unit;     // items per workgroup
+  int32_t launch;   // workgroups to launch: 8 x the longest band
+};
 
 // A segment: plan-order visibilities [start, start+count) of one data
 // block whose first tap lies in one grid tile.
@@ -88,7 +115,7 @@ struct ppd_plan {
   std::vector<ppd::Seg> segs_host;
   std::vector<int32_t> bseg_off;           // [d+1] into bseg_ids
   int n_items = 0, n_segs = 0;
-  int n_launch = 0;                        // item launches padded to an XCD multiple
+  ppd::XcdSplit split1{}, split_degrid{}, split_grid{};   // 1, PPD_DEGRID_RUN, PPD_GRIDM_RUN x WPG items per workgroup
   int n_tiles = 0, n_tile_launch = 0;
 
   // device: coverage and plan tables
@@ -129,6 +156,16 @@ struct ppd_plan {
   int32_t* sec_coff = nullptr;             // [d + 1] chunks of block j: [sec_coff[j], sec_coff[j+1])
   double* sec_part = nullptr;              // [2][2][n_sec_chunks] S2, S3 partials, two passes
   double* sec_nu = nullptr;                // [2][d] nu of the last two Newton passes
+  // persistent Algorithm 2 middle steps (one launch, state in registers):
+  // workgroup g holds plan-order points [g PA_CHUNK, (g+1) PA_CHUNK)
+  int pa_groups = 0;                       // workgroups of the persistent launch
+  bool pa_ok = false;                      // every workgroup co-resident and within PA_MAXB blocks
+  int32_t* voff_d = nullptr;               // [d+1] block offsets (plan order)
+  int32_t* pa_wgb0 = nullptr;              // [pa_groups] first block of each workgroup
+  int32_t* pa_gfirst = nullptr;            // [d] first workgroup of each block
+  int32_t* pa_glast = nullptr;             // [d] last workgroup of each block
+  double* pa_part = nullptr;               // [2][pa_groups][PA_MAXB] per-workgroup block partials
+  uint32_t* pa_sync = nullptr;             // [4] barrier arrivals, exits, give-up flag, spare
   double* part = nullptr;                  // [2][n_segs] block-norm partials
   double* rpart = nullptr;                 // [n_segs] residual partials
   double* eps_d = nullptr;                 // [d]
@@ -154,10 +191,11 @@ struct ppd_plan {
   size_t ws_bytes = 0, ws_used = 0;
   bool ws_measure = false;
 
-  // graph replay of one iteration
-  hipGraphExec_t graph_exec = nullptr;
-  hipGraph_t graph = nullptr;
-  std::string graph_key;
+  // graph replay of one iteration: slot 0 without, slot 1 with the
+  // statistics partials
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  std::string graph_key[2];
 
   // optional per-launch timing
   bool timing = false;
@@ -200,11 +238,20 @@ struct DualArgs {
 int degrid_dual(ppd_plan* p, const DualArgs& a, double* part_out);   // grid_f -> gabuf; part_out NULL: no Algorithm 2 partials
 int grid_plain(ppd_plan* p, const float2* v);                 // v -> grid_a (accumulate)
 int grid_dual(ppd_plan* p, const DualArgs& a, const double* part_in);  // dual finish + grid
+int grid_dual_factored(ppd_plan* p, const DualArgs& a);   // the same with the block factors already in bfac
 
 int plain_dual(ppd_plan* p, const DualArgs& a);               // per-block unfused dual update
 // Per-block projection factors of P_B from per-segment partials of
 // ||q - y||^2: bfac[j] = (min(1, eps_j / r_j), r_j <= eps_j), r_j the block norm.
 int block_factors(ppd_plan* p, const double* part);
+// The n_itr - 1 middle Algorithm 2 steps of the fused form in one persistent
+// launch (needs p->pa_ok and the first step's factors in bfac; leaves the
+// last step's factors in bfac).  spin_limit bounds each grid-barrier wait
+// (0: default).
+int alg2_persistent(ppd_plan* p, const DualArgs& a, int spin_limit);
+// Maximum co-resident workgroups of the persistent launch on the current
+// device (0 if it cannot be determined).
+int alg2_persistent_capacity();
 // n_newton Newton steps of the exact prox per block; nu_j in bfac[j].x.
 // The prox argument is w if non-NULL, else U^-1 v + ga (see dual_arg).
 int secular_solve(ppd_plan* p, const double2* w, const float2* v, const float2* ga, const float2* y,
@@ -254,7 +301,7 @@ __host__ __device__ inline void kb_weights(float s, const float* __restrict__ c,
 }
 static_assert(KB_DEG % 2 == 1, "even / odd split assumes an odd degree");
 
-// Algorithm 3 step 10 argument w = U^-1 v + Theta G a in FP64; the fused form
+// argument of the data-dual update of Algorithm 3, w = U^-1 v + Theta G a, in FP64; the fused form
 // stores Theta G a (complex64) and rebuilds w where it is needed, bitwise
 // the same each time.
 __device__ __forceinline__ double2 dual_arg(float2 v, double U, float2 ga) {
@@ -303,6 +350,14 @@ __device__ __forceinline__ int seg_of(int li, int s, const int* pre) {
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
+}
+
+// The unit (first item / unit) a workgroup takes in a work-balanced XCD
+// split, or -1 when its XCD's band has no unit left for it.
+__device__ __forceinline__ int xcd_unit(int bid, const XcdSplit& s) {
+  const int k = bid % MAX_XCD;
+  const int u = s.off[k] + bid / MAX_XCD;
+  return u < s.off[k + 1] ? u : -1;
 }
 
 // XCD-aware remap: consecutive workgroup ids go round-robin over the XCDs;

@@ -6,7 +6,7 @@
 // (blockIdx.z = basis; the Dirac basis rides in the first launch): a
 // workgroup stages the periodic input region of its output tile in LDS,
 // filters the columns, then the rows, and writes the four sub-bands.  In
-// the dual mode (Algorithm 3 steps 19-20) every final coefficient c is
+// the dual mode (the sparsity dual update of Algorithm 3) every final coefficient c is
 // consumed in place: u <- u + lambda (clip(u + c, +-alpha) - u).
 // Synthesis is the transpose, one launch per level; the last level sums the
 // 8 reconstructions and the Dirac part in registers (no atomics) and applies
@@ -128,7 +128,7 @@ __device__ void dwt_tile(const float* __restrict__ src, int sstride, float scale
     if (MODE == A_PLAIN) {
       ub[pos[s]] = cs;
     } else {
-      // Algorithm 3 steps 19-20 on the coefficient of Psi^H x~
+      // the sparsity dual update of Algorithm 3 on the coefficient of Psi^H x~
       const float cl = fminf(fmaxf(uo[s] + cs, -alpha), alpha);
       ub[pos[s]] = uo[s] + lambda * (cl - uo[s]);
     }
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float*
   const int k0y = blockIdx.y * toy, k0x = blockIdx.x * tox;
   const int q = blockIdx.z + 1;   // 1..8 wavelets, 9 = Dirac (level 1 only)
   const float third = 1.0f / 3.0f;
-  // randomised updates (Algorithm 3 steps 23-26): an inactive basis keeps
+  // randomised updates (Algorithm 3 with a random set of bases): an inactive basis keeps
   // its u_i (basis index 0 is the Dirac basis)
   if (active && !active[q == 9 ? 0 : q]) return;
   if (q == 9) {

@@ -25,6 +25,7 @@ ORDER_PLAN, ORDER_USER = 0, 1
 SARA_ANALYSIS, SARA_SYNTHESIS, SARA_DUAL = 0, 1, 2
 FORM_FUSED, FORM_PLAIN = 0, 1
 PROX_FB, PROX_EXACT = 0, 1
+PERSIST_AUTO, PERSIST_OFF = 0, 1
 
 c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -39,7 +40,8 @@ class PlanDesc(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("Kx", c_int32), ("Ky", c_int32), ("M", c_int64),
                 ("d", c_int32), ("levels", c_int32), ("tile", c_int32), ("chunk", c_int32),
-                ("n_chunks", c_int32), ("kb_beta", c_double), ("device_bytes", ctypes.c_size_t)]
+                ("n_chunks", c_int32), ("kb_beta", c_double), ("device_bytes", ctypes.c_size_t),
+                ("persistent", c_int32), ("pad_", c_int32)]
 
 
 class State(ctypes.Structure):
@@ -53,8 +55,8 @@ class Params(ctypes.Structure):
                 ("use_graph", c_int32), ("pad_", c_int32), ("y", c_void_p), ("U", c_void_p),
                 ("eps", ctypes.POINTER(c_double)), ("x_true", c_void_p), ("W", c_void_p),
                 ("prox", c_int32), ("n_newton", c_int32), ("block_active", c_void_p),
-                ("basis_active", c_void_p), ("stats_every", c_int32), ("pad2_", c_int32),
-                ("stats_history", c_void_p)]
+                ("basis_active", c_void_p), ("persistent", c_int32), ("spin_limit", c_int32),
+                ("stats_every", c_int32), ("pad2_", c_int32), ("stats_history", c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -420,47 +422,80 @@ class PPDState:
         return c
 
 
-def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, tau=0.49, eta=1.0, zeta=1.0,
-                lam=1.0, alpha=1e-4, mu=1.0, n_itr=1, form=FORM_FUSED, use_graph=False, x_true=None,
-                prox=PROX_FB, n_newton=0, block_active=None, basis_active=None,
-                stats: bool = True, W=None, stats_every: int = 0, stats_history=None):
+class Iteration:
+    """Algorithm 3 on `state` with its arguments checked and marshalled once
+    (see ppd_iterate for their meaning): run(n_iter) only calls the library,
+    as a serving loop or a timed region would."""
+
+    def __init__(self, plan: Plan, state: PPDState, y, U, eps, *, tau=0.49, eta=1.0, zeta=1.0, lam=1.0,
+                 alpha=1e-4, mu=1.0, n_itr=1, form=FORM_FUSED, use_graph=False, x_true=None, prox=PROX_FB,
+                 n_newton=0, block_active=None, basis_active=None, W=None, stats_every: int = 0,
+                 stats_history=None, persistent: int = PERSIST_AUTO, spin_limit: int = 0):
+        import torch
+        _need(y, torch.complex64, plan.M, "y")
+        _need(U, torch.float64, plan.M, "U")
+        for k, dt, n in (("x", torch.float32, plan.N), ("xt", torch.float32, plan.N),
+                         ("v", torch.complex64, plan.M), ("u", torch.float32, 9 * plan.N),
+                         ("z", torch.complex128, plan.M)):
+            _need(getattr(state, k), dt, n, k)
+        if x_true is not None:
+            _need(x_true, torch.float32, plan.N, "x_true")
+        if W is not None:
+            _need(W, torch.float32, 9 * plan.N, "W")
+        if block_active is not None:
+            _need(block_active, torch.uint8, plan.d, "block_active")
+        if basis_active is not None:
+            _need(basis_active, torch.uint8, 9, "basis_active")
+        if stats_history is not None:
+            if stats_every <= 0:
+                raise ValueError("stats_history needs stats_every > 0")
+            import torch as _t
+            if not isinstance(stats_history, _t.Tensor) or not stats_history.is_cuda or \
+                    stats_history.dtype != _t.float64 or not stats_history.is_contiguous():
+                raise ValueError("stats_history must be a contiguous float64 CUDA tensor")
+        self.plan, self.state = plan, state
+        self._keep = (y, U, x_true, W, block_active, basis_active, stats_history)
+        self._hist_rows = None if stats_history is None else stats_history.numel() // (8 + plan.d)
+        self._stats_every = int(stats_every)
+        self._eps, ep = _eps_arg(plan, eps)
+        self._st = State(_ptr(state.x), _ptr(state.xt), _ptr(state.v), _ptr(state.u), _ptr(state.z), state.iter)
+        self._prm = Params(tau, eta, zeta, lam, alpha, mu, n_itr, form, int(use_graph), 0, _ptr(y), _ptr(U), ep,
+                           _ptr(x_true), _ptr(W), int(prox), int(n_newton), _ptr(block_active),
+                           _ptr(basis_active), int(persistent), int(spin_limit), int(stats_every), 0,
+                           _ptr(stats_history))
+        self._out = Stats()
+        self._res = (c_double * plan.d)()
+        self._fn = lib().ppd_iterate
+
+    def run(self, n_iter: int, stats: bool = True):
+        """n_iter iterations; returns the last iteration's statistics (or None)."""
+        if self._hist_rows is not None and self._hist_rows < n_iter // self._stats_every:
+            raise ValueError(f"stats_history holds {self._hist_rows} rows, {n_iter // self._stats_every} needed")
+        self._st.iter = self.state.iter
+        _check("ppd_iterate", self._fn(self.plan.handle, ctypes.byref(self._st), ctypes.byref(self._prm),
+                                       int(n_iter), ctypes.byref(self._out) if stats else None,
+                                       self._res if stats else None))
+        self.state.iter = int(self._st.iter)
+        if not stats:
+            return None
+        o = self._out
+        return {"iter": int(o.iter), "rel_change": o.rel_change, "x_norm": o.x_norm, "snr_db": o.snr_db,
+                "residual_max": o.residual_max, "residual": np.array(self._res[:])}
+
+
+def ppd_iterate(plan: Plan, state: PPDState, y, U, eps, n_iter: int, *, stats: bool = True, **kw):
     """Run n_iter iterations of Algorithm 3; returns a statistics dict (or None).
-    With stats_every > 0 the statistics of every stats_every-th iteration are
-    also reduced on the device during the call, into stats_history (a float64
-    tensor of n_iter // stats_every rows of 8 + d) if given."""
-    import torch
-    _need(y, torch.complex64, plan.M, "y")
-    _need(U, torch.float64, plan.M, "U")
-    for k, dt, n in (("x", torch.float32, plan.N), ("xt", torch.float32, plan.N),
-                     ("v", torch.complex64, plan.M), ("u", torch.float32, 9 * plan.N),
-                     ("z", torch.complex128, plan.M)):
-        _need(getattr(state, k), dt, n, k)
-    if x_true is not None:
-        _need(x_true, torch.float32, plan.N, "x_true")
-    if W is not None:
-        _need(W, torch.float32, 9 * plan.N, "W")
-    if block_active is not None:
-        _need(block_active, torch.uint8, plan.d, "block_active")
-    if basis_active is not None:
-        _need(basis_active, torch.uint8, 9, "basis_active")
-    if stats_history is not None:
-        if stats_every <= 0:
-            raise ValueError("stats_history needs stats_every > 0")
-        _need(stats_history, torch.float64, (n_iter // stats_every) * (8 + plan.d), "stats_history")
-    e, ep = _eps_arg(plan, eps)
-    st = State(_ptr(state.x), _ptr(state.xt), _ptr(state.v), _ptr(state.u), _ptr(state.z), state.iter)
-    prm = Params(tau, eta, zeta, lam, alpha, mu, n_itr, form, int(use_graph), 0, _ptr(y), _ptr(U), ep,
-                 _ptr(x_true), _ptr(W), int(prox), int(n_newton), _ptr(block_active), _ptr(basis_active),
-                 int(stats_every), 0, _ptr(stats_history))
-    out = Stats()
-    res = (c_double * plan.d)()
-    _check("ppd_iterate", lib().ppd_iterate(plan.handle, ctypes.byref(st), ctypes.byref(prm), int(n_iter),
-                                            ctypes.byref(out) if stats else None, res if stats else None))
-    state.iter = int(st.iter)
-    if not stats:
-        return None
-    return {"iter": int(out.iter), "rel_change": out.rel_change, "x_norm": out.x_norm,
-            "snr_db": out.snr_db, "residual_max": out.residual_max, "residual": np.array(res[:])}
+    Keywords: tau, eta, zeta, lam, alpha, mu, n_itr, form, use_graph, x_true,
+    prox, n_newton, block_active, basis_active, W, stats_every, stats_history,
+    persistent, spin_limit (see Iteration and ppd_params).  With stats_every > 0 the statistics of every
+    stats_every-th iteration are also reduced on the device during the call,
+    into stats_history (a float64 tensor of n_iter // stats_every rows of
+    8 + d) if given."""
+    hist = kw.get("stats_history")
+    if hist is not None and kw.get("stats_every", 0) > 0:
+        import torch
+        _need(hist, torch.float64, (n_iter // kw["stats_every"]) * (8 + plan.d), "stats_history")
+    return Iteration(plan, state, y, U, eps, **kw).run(n_iter, stats=stats)
 
 
 def randomised_ppd(plan: Plan, state: PPDState, y, U, eps, block_masks, basis_masks, **kw):
