@@ -251,8 +251,12 @@ typedef struct {
                                       points fit the device at once (about
                                       2M visibilities) and no 2048 consecutive
                                       plan-order points span more than 4
-                                      blocks; PPD_PERSIST_OFF (1): one launch
-                                      pair per step                          */
+                                      blocks (the launch waits for the SARA
+                                      branch of its iteration and needs the
+                                      device to itself: work that other
+                                      streams run beside it can make a
+                                      barrier give up); PPD_PERSIST_OFF (1):
+                                      one launch pair per step               */
   int32_t spin_limit;              /* polls of a persistent grid barrier
                                       before it gives up (0: 2^20); a give-up
                                       makes every workgroup finish and the

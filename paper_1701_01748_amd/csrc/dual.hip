@@ -161,23 +161,52 @@ struct PaArgs {
   uint32_t* sync;
 };
 
-// sync[0] counts arrivals over the launch (barrier s completes at
-// (s + 1) G), sync[2] is the give-up flag.  Called by one thread of the
-// workgroup, after it has stored the workgroup's partials.  Returns 1 when
-// every workgroup has arrived, 0 after a give-up.
-__device__ int grid_barrier(uint32_t* sync, uint32_t target, int spin_limit) {
-  __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Arrivals are counted in two levels, so that no single counter takes
+// every workgroup's atomic (one counter for ~600 workgroups cost ~30 us per
+// barrier): workgroup g counts on sub-counter g mod PA_NSUB, and the
+// workgroup completing a sub-counter's count for this barrier counts on the
+// top counter; waiters poll the top counter.  Counts grow over the launch
+// (barrier s completes a sub-counter at (s + 1) x its members and the top
+// counter at (s + 1) x the sub-counters in use).  sync[0] top, sync[1]
+// exits, sync[2] give-up flag, sync[PA_SUB0 + PA_SUBSTRIDE k] sub-counter k.
+// Called by one thread of the workgroup after it has published the
+// workgroup's partials with atomic exchanges.  No cache-wide write-back or
+// invalidate is used (one per workgroup and barrier cost ~50 us per step):
+// everything the barrier publishes goes through device-scope atomics,
+// which are performed at the device's coherence point, and is read with
+// device-coherent loads.  The wait for all outstanding memory operations
+// makes the exchanges complete (acknowledged) before the arrival is
+// counted.  Returns 1 when every workgroup has arrived, 0 after a give-up.
+__device__ int grid_barrier(uint32_t* sync, int g, int G, int s, int spin_limit) {
+  const int nsub = min(G, PA_NSUB);
+  const int sub = g % nsub;
+  const uint32_t members = uint32_t((G - sub + nsub - 1) / nsub);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const uint32_t old = __hip_atomic_fetch_add(&sync[PA_SUB0 + PA_SUBSTRIDE * sub], 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+  if (old + 1u == uint32_t(s + 1) * members) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  const uint32_t target = uint32_t(s + 1) * uint32_t(nsub);
   int polls = 0;
+  int ok = 1;
   while (__hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    if (__hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return 0;
+    if ((polls & 31) == 31 && __hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+      ok = 0;
+      break;
+    }
     if (++polls > spin_limit) {
       __hip_atomic_store(&sync[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return 0;
+      ok = 0;
+      break;
     }
-    __builtin_amdgcn_s_sleep(4);
+    __builtin_amdgcn_s_sleep(2);
   }
-  (void)__hip_atomic_load(&sync[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-  return 1;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  return ok;
 }
 
 __global__ __launch_bounds__(PA_THREADS) void k_alg2_persistent(PaArgs a) {
@@ -246,9 +275,9 @@ __global__ __launch_bounds__(PA_THREADS) void k_alg2_persistent(PaArgs a) {
     double* part = a.part + size_t(s & 1) * size_t(a.G) * PA_MAXB;
     if (tid == 0) {
       for (int b = 0; b < nb; ++b)
-        __hip_atomic_store(&part[size_t(g) * PA_MAXB + b], ((red[0][b] + red[1][b]) + red[2][b]) + red[3][b],
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      (void)grid_barrier(a.sync, uint32_t(s + 1) * uint32_t(a.G), a.spin_limit);
+        (void)__hip_atomic_exchange(&part[size_t(g) * PA_MAXB + b], ((red[0][b] + red[1][b]) + red[2][b]) + red[3][b],
+                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      (void)grid_barrier(a.sync, g, a.G, s, a.spin_limit);
     }
     __syncthreads();
     // the factors of this workgroup's blocks from all their workgroups' partials
@@ -279,10 +308,12 @@ __global__ __launch_bounds__(PA_THREADS) void k_alg2_persistent(PaArgs a) {
   if (tid < nb && a.gfirst[b0 + tid] == g) a.bfac[b0 + tid] = fac[tid];
   // the last workgroup out clears the arrival and exit counts for the next launch
   if (tid == 0) {
-    const uint32_t out = __hip_atomic_fetch_add(&a.sync[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t out = __hip_atomic_fetch_add(&a.sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (out == uint32_t(a.G) - 1u) {
       __hip_atomic_store(&a.sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&a.sync[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int k = 0; k < PA_NSUB; ++k)
+        __hip_atomic_store(&a.sync[PA_SUB0 + PA_SUBSTRIDE * k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

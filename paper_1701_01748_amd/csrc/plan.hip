@@ -605,7 +605,7 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   A(dalloc(p, &p->pa_gfirst, p->d));
   A(dalloc(p, &p->pa_glast, p->d));
   A(dalloc(p, &p->pa_part, 2 * size_t(p->pa_groups) * PA_MAXB));
-  A(dalloc(p, &p->pa_sync, 4));
+  A(dalloc(p, &p->pa_sync, PA_SYNC_WORDS));
   A(dalloc(p, &p->part, 2 * size_t(p->n_segs)));
   A(dalloc(p, &p->rpart, p->n_segs));
   A(dalloc(p, &p->eps_d, p->d));
@@ -665,8 +665,8 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   up(p->pa_gfirst, gfirst.data(), 4 * gfirst.size());
   up(p->pa_glast, glast.data(), 4 * glast.size());
   {
-    const uint32_t zeros[4] = {0u, 0u, 0u, 0u};
-    up(p->pa_sync, zeros, sizeof(zeros));
+    const std::vector<uint32_t> zeros(PA_SYNC_WORDS, 0u);
+    up(p->pa_sync, zeros.data(), sizeof(uint32_t) * zeros.size());
   }
   // the persistent launch needs all its workgroups on the device at once
   if (st == PPD_OK) {

@@ -41,6 +41,10 @@ constexpr int PA_THREADS = 256;   // persistent Algorithm 2: threads per workgro
 constexpr int PA_PER = 8;         // points per thread held in registers
 constexpr int PA_CHUNK = PA_THREADS * PA_PER;
 constexpr int PA_MAXB = 4;        // data blocks one workgroup's points may span
+constexpr int PA_NSUB = 32;       // sub-counters of its grid barrier
+constexpr int PA_SUB0 = 32;       // first sub-counter in the sync array (uint32 index)
+constexpr int PA_SUBSTRIDE = 32;  // one 128-byte line per sub-counter
+constexpr int PA_SYNC_WORDS = PA_SUB0 + PA_SUBSTRIDE * PA_NSUB;
 #ifndef PPD_FOLD_HEAVY
 #define PPD_FOLD_HEAVY 16
 #endif
@@ -165,7 +169,7 @@ struct ppd_plan {
   int32_t* pa_gfirst = nullptr;            // [d] first workgroup of each block
   int32_t* pa_glast = nullptr;             // [d] last workgroup of each block
   double* pa_part = nullptr;               // [2][pa_groups][PA_MAXB] per-workgroup block partials
-  uint32_t* pa_sync = nullptr;             // [4] barrier arrivals, exits, give-up flag, spare
+  uint32_t* pa_sync = nullptr;             // [PA_SYNC_WORDS] barrier top count, exits, give-up flag; sub-counters
   double* part = nullptr;                  // [2][n_segs] block-norm partials
   double* rpart = nullptr;                 // [n_segs] residual partials
   double* eps_d = nullptr;                 // [d]
