@@ -166,6 +166,26 @@ int ppd_reweight(ppd_plan* plan, const float* x, float omega, float* W);
 int ppd_ellipsoid_proj(ppd_plan* plan, const double* w, const float* y, const double* U,
                        const double* eps, int n_itr, double mu, double* zbar_inout);
 
+/* ppd_ellipsoid_proj for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same n_itr Algorithm 2 iterations per block, with no plan
+ * and no allocation of any kind.  Block j is the contiguous range
+ * [block_off[j], block_off[j+1]) of the arrays (any order inside a block,
+ * e.g. a plan's order); w, zbar_inout: [M] complex128; y: [M] complex64;
+ * U: [M] float64 > 0 (DEVICE, M = block_off[d]); block_off: HOST [d+1]
+ * int64, 0 = off[0] < off[1] < ...; eps: HOST [d] float64 > 0; mu > 0;
+ * stream: hipStream_t (NULL = default stream).  Limits: d <= 4096 and at
+ * most 65536 chunks of 8192 points (about 5.4e8 visibilities); beyond them
+ * PPD_EINVAL and nothing is launched.  The per-block partial sums and
+ * factors live in one fixed device array of about 0.7 MiB that each GPU the
+ * library runs on holds until the process ends; every call on a GPU uses
+ * that GPU's array, so calls that overlap on one GPU (on different streams
+ * or host threads) race and must be ordered by the caller.  Asynchronous on
+ * `stream` (the host tables are staged by the runtime before it returns). */
+int ppd_ellipsoid_proj_noalloc(const double* w, const float* y, const double* U, int32_t d,
+                               const int64_t* block_off, const double* eps, int n_itr, double mu,
+                               double* zbar_inout, void* stream);
+
 /* The prox of eq. elip-proj-1 itself (the exact alternative the paper
  * names next to Algorithm 2, Sec. 4.1): per block j,
  *     z = argmin_{||z - y_j|| <= eps_j} (w - z)^H U_j (w - z) / 2

@@ -84,6 +84,8 @@ _PROTOS = {
     "ppd_reweight": (c_int32, [c_void_p, c_void_p, ctypes.c_float, c_void_p]),
     "ppd_ellipsoid_proj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double),
                                      c_int32, c_double, c_void_p]),
+    "ppd_ellipsoid_proj_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(c_int64),
+                                             ctypes.POINTER(c_double), c_int32, c_double, c_void_p, c_void_p]),
     "ppd_prox_metric": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_int32,
                                   c_void_p, c_void_p]),
     "ppd_uniform_weights": (c_int32, [c_void_p, c_void_p]),
@@ -359,6 +361,29 @@ def ppd_ellipsoid_proj(plan: Plan, w, y, U, eps, n_itr: int, mu: float, z):
     e, ep = _eps_arg(plan, eps)
     _check("ppd_ellipsoid_proj", lib().ppd_ellipsoid_proj(plan.handle, _ptr(w), _ptr(y), _ptr(U), ep,
                                                           int(n_itr), float(mu), _ptr(z)))
+    return z
+
+
+def ppd_ellipsoid_proj_noalloc(w, y, U, block_off, eps, n_itr: int, mu: float, z, stream=None):
+    """ppd_ellipsoid_proj without a plan or any device allocation: blocks are
+    the contiguous ranges of block_off (HOST); in place on z (complex128)."""
+    import torch
+    off = np.ascontiguousarray(block_off, dtype=np.int64)
+    d = off.size - 1
+    M = int(off[-1]) if d >= 1 else 0
+    _need(w, torch.complex128, M, "w")
+    _need(y, torch.complex64, M, "y")
+    _need(U, torch.float64, M, "U")
+    _need(z, torch.complex128, M, "z")
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    if e.shape != (d,):
+        raise ValueError(f"eps must have shape ({d},)")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check("ppd_ellipsoid_proj_noalloc",
+           lib().ppd_ellipsoid_proj_noalloc(_ptr(w), _ptr(y), _ptr(U), d, off.ctypes.data_as(ctypes.POINTER(c_int64)),
+                                            e.ctypes.data_as(ctypes.POINTER(c_double)), int(n_itr), float(mu),
+                                            _ptr(z), c_void_p(int(stream.cuda_stream))))
     return z
 
 
