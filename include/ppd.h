@@ -326,6 +326,57 @@ typedef struct {
 int ppd_iterate(ppd_plan* plan, ppd_state* state, const ppd_params* params, int n_iter,
                 ppd_stats* stats, double* residual);
 
+/* ---- differentiable pieces of Algorithm 3 (unrolled iterations) ------- */
+/* One iteration of Algorithm 3 is, in the library's data flow,
+ *   g = Theta G F Z x~ (ppd_phi),   (v', z') = dual update (g, v, z),
+ *   c = Psi^H x~ (ppd_sara),        u' = sparsity update (u, c),
+ *   x' , x~' = primal update (x, Re Phi^H v' (ppd_phit), Psi u' (ppd_sara)).
+ * Each update below has a vector-Jacobian product (VJP): given the
+ * gradients of a real loss with respect to its outputs, the gradients with
+ * respect to its inputs, in torch's convention for complex arrays
+ * (dL/dRe + i dL/dIm).  U, eps, alpha and the step sizes are constants.
+ * All arrays are DEVICE arrays of the plan's sizes; no output may alias an
+ * input.  Asynchronous on the plan's stream. */
+
+/* Data-dual update (the generalised Moreau step of Algorithm 3 with
+ * Algorithm 2 for the prox, Sec. 4.1), per block j of plan-order points:
+ * w = U^-1 v + g, z_0 = z, z_s = P_B(z_{s-1} - mu U (z_{s-1} - w)) for
+ * s = 1..n_itr, v' = v + lambda (U (w - z_n) - v), z' = z_n.  g, y, v,
+ * v_out: [M] complex64; U: [M] float64; z, z_out: [M] complex128; eps: HOST
+ * [d].  zs: optional [n_itr][M] complex128 receiving z_1..z_n (needed by the
+ * VJP); FP64 arithmetic and block norms. */
+int ppd_dual_update(ppd_plan* plan, const float* g, const float* y, const double* U, const double* eps,
+                    const float* v, const double* z, int n_itr, double mu, double lambda, float* v_out,
+                    double* z_out, double* zs);
+/* VJP of ppd_dual_update (same inputs and the zs it wrote): from gv_out
+ * ([M] complex64, NULL = 0) and gz_out ([M] complex128, NULL = 0), the
+ * gradients g_g, g_v, g_y ([M] complex64, each optional) and g_z ([M]
+ * complex128, required).  Through P_B the Jacobian is the identity inside
+ * the ball and (eps / r)(I - d d^T / r^2) outside (d = q - y, r = ||d||),
+ * applied with a block inner product per step. */
+int ppd_dual_update_vjp(ppd_plan* plan, const float* g, const float* y, const double* U, const double* eps,
+                        const float* v, const double* z, int n_itr, double mu, double lambda, const double* zs,
+                        const float* gv_out, const double* gz_out, float* g_g, float* g_v, double* g_z,
+                        float* g_y);
+/* Sparsity dual update per coefficient ([9][ny][nx] float32):
+ * u' = u + lambda (clip(u + c, +-alpha) - u), the clip being (I - S_alpha) of
+ * Sec. 3.3.  VJP: g_u = (1 - lambda + lambda m) g_out, g_c = lambda m g_out,
+ * m = [|u + c| < alpha] (g_u, g_c optional). */
+int ppd_sparsity_update(ppd_plan* plan, const float* u, const float* c, float alpha, float lambda, float* u_out);
+int ppd_sparsity_update_vjp(ppd_plan* plan, const float* u, const float* c, float alpha, float lambda,
+                            const float* g_out, float* g_u, float* g_c);
+/* Primal update per pixel ([ny][nx] float32; FP64 arithmetic):
+ * xbar = P_C(x - tau (eta a + zeta b)), x' = x + lambda (xbar - x),
+ * x~' = 2 xbar - x, with a = Re Phi^H v' and b = Psi u'.  VJP from gx_out,
+ * gxt_out (NULL = 0): with m = [x - tau (eta a + zeta b) > 0] and
+ * gbar = m (lambda gx_out + 2 gxt_out), g_x = (1 - lambda) gx_out - gxt_out
+ * + gbar, g_a = -tau eta gbar, g_b = -tau zeta gbar (each optional). */
+int ppd_primal_update(ppd_plan* plan, const float* x, const float* a, const float* b, double tau, double eta,
+                      double zeta, double lambda, float* x_out, float* xt_out);
+int ppd_primal_update_vjp(ppd_plan* plan, const float* x, const float* a, const float* b, double tau, double eta,
+                          double zeta, double lambda, const float* gx_out, const float* gxt_out, float* g_x,
+                          float* g_a, float* g_b);
+
 /* ---- per-kernel timing (HIP events around each launch) ----------------- */
 /* When enabled, the plan records a pair of HIP events around every kernel
  * it launches (not inside captured graphs).  ppd_timing_read synchronises

@@ -10,9 +10,11 @@ complex tensor y is grad = dL/dRe(y) + i dL/dIm(y); with it
     x = Re(Phi^H y)      ->  grad_y = Phi grad_x
 
 `unrolled_ppd` composes K iterations of Algorithm 3 from these operators and
-torch element-wise operations (the proximity operators are piecewise smooth:
-clip, max(0, .) and the l2-ball projection), optionally checkpointing each
-iteration so memory stays at one iteration's activations.
+the library's three updates (data dual, sparsity dual, primal), whose
+backward passes are the library's VJP kernels: the l2-ball projection's
+Jacobian per block, the clip mask and the positivity mask (the proximity
+operators are piecewise smooth).  Each iteration can be checkpointed, so
+memory stays at one iteration's activations.
 """
 from __future__ import annotations
 
@@ -97,47 +99,88 @@ def multichannel_fidelity(plans: Sequence, x, ys: Sequence):
     return sum(data_fidelity(p, x, y) for p, y in zip(plans, ys))
 
 
-def _proj_ball(q, y, eps: float):
-    """P_B (Sec. 3.3, eq. proj-L2) for one block, differentiable."""
-    d = q - y
-    r = torch.sqrt((d.real ** 2 + d.imag ** 2).sum())
-    scale = torch.clamp(eps / r, max=1.0)
-    return y + d * scale
+class DualUpdateFn(torch.autograd.Function):
+    """(v', z') of the data-dual update from g = Theta G F Z x~, v, z and y;
+    backward: the library's VJP kernels (the P_B Jacobian per block)."""
+
+    @staticmethod
+    def forward(ctx, g, v, z, y, plan, U, eps, n_itr, mu, lam):
+        g, v, z, y = (t.detach().contiguous() for t in (g, v, z, y))
+        v_out, z_out, zs = P.ppd_dual_update(plan, g, y, U, eps, v, z, n_itr, mu, lam, keep=True)
+        ctx.save_for_backward(g, v, z, y, zs)
+        ctx.args = (plan, U, eps, n_itr, mu, lam)
+        return v_out, z_out
+
+    @staticmethod
+    def backward(ctx, gv, gz):
+        g, v, z, y, zs = ctx.saved_tensors
+        plan, U, eps, n_itr, mu, lam = ctx.args
+        gv = None if gv is None else gv.contiguous().to(torch.complex64)
+        gz = None if gz is None else gz.contiguous().to(torch.complex128)
+        g_g, g_v, g_z, g_y = P.ppd_dual_update_vjp(plan, g, y, U, eps, v, z, n_itr, mu, lam, zs, gv, gz)
+        return g_g, g_v, g_z, g_y, None, None, None, None, None, None
 
 
-def ppd_iteration(plan, block_off, y, U, eps, x, xt, v, u, z, *, tau: float, eta: float, zeta: float = 1.0,
+class SparsityUpdateFn(torch.autograd.Function):
+    """u' = u + lambda (clip(u + c, +-alpha) - u); backward: the clip mask."""
+
+    @staticmethod
+    def forward(ctx, u, c, plan, alpha, lam):
+        u, c = u.detach().contiguous(), c.detach().contiguous()
+        ctx.save_for_backward(u, c)
+        ctx.args = (plan, alpha, lam)
+        return P.ppd_sparsity_update(plan, u, c, alpha, lam)
+
+    @staticmethod
+    def backward(ctx, g):
+        u, c = ctx.saved_tensors
+        plan, alpha, lam = ctx.args
+        g_u, g_c = P.ppd_sparsity_update_vjp(plan, u, c, alpha, lam, g.contiguous().to(torch.float32))
+        return g_u, g_c, None, None, None
+
+
+class PrimalUpdateFn(torch.autograd.Function):
+    """(x', x~') of the primal update from x, a = Re Phi^H v', b = Psi u';
+    backward: the P_C mask."""
+
+    @staticmethod
+    def forward(ctx, x, a, b, plan, tau, eta, zeta, lam):
+        x, a, b = (t.detach().contiguous() for t in (x, a, b))
+        ctx.save_for_backward(x, a, b)
+        ctx.args = (plan, tau, eta, zeta, lam)
+        return P.ppd_primal_update(plan, x, a, b, tau, eta, zeta, lam)
+
+    @staticmethod
+    def backward(ctx, gx, gxt):
+        x, a, b = ctx.saved_tensors
+        plan, tau, eta, zeta, lam = ctx.args
+        gx = None if gx is None else gx.contiguous().to(torch.float32)
+        gxt = None if gxt is None else gxt.contiguous().to(torch.float32)
+        g_x, g_a, g_b = P.ppd_primal_update_vjp(plan, x, a, b, tau, eta, zeta, lam, gx, gxt)
+        return g_x, g_a, g_b, None, None, None, None, None
+
+
+def ppd_iteration(plan, y, U, eps, x, xt, v, u, z, *, tau: float, eta: float, zeta: float = 1.0,
                   lam: float = 1.0, alpha: float = 1e-4, mu: float = 1.0, n_itr: int = 1):
-    """One iteration of Algorithm 3 as differentiable torch code (plan order).
+    """One differentiable iteration of Algorithm 3 in the library's data flow
+    (plan order): the data-dual update of every block on Theta G F Z x~, the
+    sparsity dual update on Psi^H x~, and the primal update on
+    Re Phi^H v' and Psi u'; every forward and backward step is a HIP kernel.
 
     x, xt: (ny, nx) float32; v: (M,) complex64; u: (9, ny, nx) float32;
-    z: (M,) complex128; y: (M,) complex64; U: (M,) float64; eps: (d,) floats.
+    z: (M,) complex128; y: (M,) complex64; U: (M,) float64; eps: (d,).
     Returns the new (x, xt, v, u, z)."""
-    g = phi(plan, xt).to(torch.complex128)                          # step 4 + Theta G
-    w = v.to(torch.complex128) / U + g                              # step 10 argument
-    yd = y.to(torch.complex128)
-    zs, vs = [], []
-    for j in range(len(block_off) - 1):
-        s = slice(int(block_off[j]), int(block_off[j + 1]))
-        zj = z[s]
-        for _ in range(n_itr):                                      # Algorithm 2
-            zj = _proj_ball(zj - mu * U[s] * (zj - w[s]), yd[s], float(eps[j]))
-        vbar = U[s] * (w[s] - zj)                                   # step 10
-        vs.append(v[s].to(torch.complex128) + lam * (vbar - v[s].to(torch.complex128)))  # step 11
-        zs.append(zj)
-    v_new = torch.cat(vs).to(torch.complex64)
-    z_new = torch.cat(zs)
-    ubar = torch.clamp(u + sara_analysis(plan, xt), -alpha, alpha)  # step 19
-    u_new = u + lam * (ubar - u)                                    # step 20
-    grad = eta * phit(plan, v_new) + zeta * sara_synthesis(plan, u_new)   # steps 12, 21
-    xbar = torch.relu(x - tau * grad)                               # step 28
-    x_new = x + lam * (xbar - x)                                    # step 29
-    xt_new = 2.0 * xbar - x                                         # step 30
+    g = phi(plan, xt)
+    v_new, z_new = DualUpdateFn.apply(g, v, z, y, plan, U, eps, n_itr, mu, lam)
+    u_new = SparsityUpdateFn.apply(u, sara_analysis(plan, xt), plan, alpha, lam)
+    x_new, xt_new = PrimalUpdateFn.apply(x, phit(plan, v_new), sara_synthesis(plan, u_new), plan, tau, eta, zeta, lam)
     return x_new, xt_new, v_new, u_new, z_new
 
 
 def unrolled_ppd(plan, block_off, y, U, eps, x0, K: int, *, checkpoint: bool = True, state=None, **params):
     """K differentiable PPD iterations from x = x~ = x0 (v = 0, u = 0, z = y
-    unless `state` = (x, xt, v, u, z) is given).  Returns the final x."""
+    unless `state` = (x, xt, v, u, z) is given).  Returns the final x.
+    block_off is accepted for compatibility (the plan holds the blocks)."""
     if state is None:
         x, xt = x0, x0
         v = torch.zeros_like(y)
@@ -148,8 +191,8 @@ def unrolled_ppd(plan, block_off, y, U, eps, x0, K: int, *, checkpoint: bool = T
     for _ in range(K):
         if checkpoint:
             x, xt, v, u, z = torch.utils.checkpoint.checkpoint(
-                lambda *s: ppd_iteration(plan, block_off, y, U, eps, *s, **params),
+                lambda *s: ppd_iteration(plan, y, U, eps, *s, **params),
                 x, xt, v, u, z, use_reentrant=False)
         else:
-            x, xt, v, u, z = ppd_iteration(plan, block_off, y, U, eps, x, xt, v, u, z, **params)
+            x, xt, v, u, z = ppd_iteration(plan, y, U, eps, x, xt, v, u, z, **params)
     return x

@@ -600,6 +600,7 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   A(dalloc(p, &p->sec_coff, coff.size()));
   A(dalloc(p, &p->sec_part, 4 * cblock.size()));
   A(dalloc(p, &p->sec_nu, 2 * size_t(p->d)));
+  A(dalloc(p, &p->du_blk, p->d));
   A(dalloc(p, &p->voff_d, p->d + 1));
   A(dalloc(p, &p->pa_wgb0, p->pa_groups));
   A(dalloc(p, &p->pa_gfirst, p->d));

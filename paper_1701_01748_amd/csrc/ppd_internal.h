@@ -160,6 +160,7 @@ struct ppd_plan {
   int32_t* sec_coff = nullptr;             // [d + 1] chunks of block j: [sec_coff[j], sec_coff[j+1])
   double* sec_part = nullptr;              // [2][2][n_sec_chunks] S2, S3 partials, two passes
   double* sec_nu = nullptr;                // [2][d] nu of the last two Newton passes
+  double4* du_blk = nullptr;               // [d] block terms of the differentiable dual update
   // persistent Algorithm 2 middle steps (one launch, state in registers):
   // workgroup g holds plan-order points [g PA_CHUNK, (g+1) PA_CHUNK)
   int pa_groups = 0;                       // workgroups of the persistent launch

@@ -93,6 +93,18 @@ _PROTOS = {
                               ctypes.POINTER(c_int32)]),
     "ppd_iterate": (c_int32, [c_void_p, ctypes.POINTER(State), ctypes.POINTER(Params), c_int32,
                               ctypes.POINTER(Stats), ctypes.POINTER(c_double)]),
+    "ppd_dual_update": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p,
+                                  c_void_p, c_int32, c_double, c_double, c_void_p, c_void_p, c_void_p]),
+    "ppd_dual_update_vjp": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p,
+                                      c_void_p, c_int32, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p]),
+    "ppd_sparsity_update": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float, c_void_p]),
+    "ppd_sparsity_update_vjp": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float, c_void_p,
+                                          c_void_p, c_void_p]),
+    "ppd_primal_update": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_double, c_double,
+                                    c_void_p, c_void_p]),
+    "ppd_primal_update_vjp": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_double,
+                                        c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ppd_timing_enable": (c_int32, [c_void_p, c_int32]),
     "ppd_timing_reset": (c_int32, [c_void_p]),
     "ppd_timing_read": (c_int32, [c_void_p, c_int32, ctypes.POINTER(ctypes.c_char_p),
@@ -423,6 +435,91 @@ def ppd_op_norm(plan: Plan, U, x0, max_iter: int = 1000, tol: float = 1e-10):
     _check("ppd_op_norm", lib().ppd_op_norm(plan.handle, _ptr(U), _ptr(x0), int(max_iter), float(tol),
                                             ctypes.byref(out), ctypes.byref(it)))
     return float(out.value), int(it.value)
+
+
+# ---- differentiable pieces of Algorithm 3 (forward and VJP) ---------------------
+
+def ppd_dual_update(plan: Plan, g, y, U, eps, v, z, n_itr: int, mu: float, lam: float, keep: bool = False):
+    """(v', z', zs) of the data-dual update; zs (n_itr x M complex128) only
+    when keep (the VJP needs it)."""
+    import torch
+    for t, dt, name in ((g, torch.complex64, "g"), (y, torch.complex64, "y"), (v, torch.complex64, "v")):
+        _need(t, dt, plan.M, name)
+    _need(U, torch.float64, plan.M, "U")
+    _need(z, torch.complex128, plan.M, "z")
+    e, ep = _eps_arg(plan, eps)
+    v_out = _alloc((plan.M,), torch.complex64)
+    z_out = _alloc((plan.M,), torch.complex128)
+    zs = _alloc((int(n_itr), plan.M), torch.complex128) if keep else None
+    _check("ppd_dual_update", lib().ppd_dual_update(plan.handle, _ptr(g), _ptr(y), _ptr(U), ep, _ptr(v), _ptr(z),
+                                                    int(n_itr), float(mu), float(lam), _ptr(v_out), _ptr(z_out),
+                                                    _ptr(zs)))
+    return v_out, z_out, zs
+
+
+def ppd_dual_update_vjp(plan: Plan, g, y, U, eps, v, z, n_itr: int, mu: float, lam: float, zs, gv_out, gz_out):
+    """Gradients (g_g, g_v, g_z, g_y) of the data-dual update."""
+    import torch
+    _need(zs, torch.complex128, int(n_itr) * plan.M, "zs")
+    if gv_out is not None:
+        _need(gv_out, torch.complex64, plan.M, "gv_out")
+    if gz_out is not None:
+        _need(gz_out, torch.complex128, plan.M, "gz_out")
+    e, ep = _eps_arg(plan, eps)
+    g_g = _alloc((plan.M,), torch.complex64)
+    g_v = _alloc((plan.M,), torch.complex64)
+    g_z = _alloc((plan.M,), torch.complex128)
+    g_y = _alloc((plan.M,), torch.complex64)
+    _check("ppd_dual_update_vjp", lib().ppd_dual_update_vjp(
+        plan.handle, _ptr(g), _ptr(y), _ptr(U), ep, _ptr(v), _ptr(z), int(n_itr), float(mu), float(lam), _ptr(zs),
+        _ptr(gv_out), _ptr(gz_out), _ptr(g_g), _ptr(g_v), _ptr(g_z), _ptr(g_y)))
+    return g_g, g_v, g_z, g_y
+
+
+def ppd_sparsity_update(plan: Plan, u, c, alpha: float, lam: float):
+    import torch
+    _need(u, torch.float32, 9 * plan.N, "u")
+    _need(c, torch.float32, 9 * plan.N, "c")
+    out = _alloc((9, plan.ny, plan.nx), torch.float32)
+    _check("ppd_sparsity_update", lib().ppd_sparsity_update(plan.handle, _ptr(u), _ptr(c), float(alpha), float(lam),
+                                                            _ptr(out)))
+    return out
+
+
+def ppd_sparsity_update_vjp(plan: Plan, u, c, alpha: float, lam: float, g_out):
+    import torch
+    _need(g_out, torch.float32, 9 * plan.N, "g_out")
+    g_u = _alloc((9, plan.ny, plan.nx), torch.float32)
+    g_c = _alloc((9, plan.ny, plan.nx), torch.float32)
+    _check("ppd_sparsity_update_vjp", lib().ppd_sparsity_update_vjp(plan.handle, _ptr(u), _ptr(c), float(alpha),
+                                                                    float(lam), _ptr(g_out), _ptr(g_u), _ptr(g_c)))
+    return g_u, g_c
+
+
+def ppd_primal_update(plan: Plan, x, a, b, tau: float, eta: float, zeta: float, lam: float):
+    import torch
+    for t, name in ((x, "x"), (a, "a"), (b, "b")):
+        _need(t, torch.float32, plan.N, name)
+    x_out = _alloc((plan.ny, plan.nx), torch.float32)
+    xt_out = _alloc((plan.ny, plan.nx), torch.float32)
+    _check("ppd_primal_update", lib().ppd_primal_update(plan.handle, _ptr(x), _ptr(a), _ptr(b), float(tau),
+                                                        float(eta), float(zeta), float(lam), _ptr(x_out),
+                                                        _ptr(xt_out)))
+    return x_out, xt_out
+
+
+def ppd_primal_update_vjp(plan: Plan, x, a, b, tau: float, eta: float, zeta: float, lam: float, gx_out, gxt_out):
+    import torch
+    for t, name in ((gx_out, "gx_out"), (gxt_out, "gxt_out")):
+        if t is not None:
+            _need(t, torch.float32, plan.N, name)
+    g_x = _alloc((plan.ny, plan.nx), torch.float32)
+    g_a = _alloc((plan.ny, plan.nx), torch.float32)
+    g_b = _alloc((plan.ny, plan.nx), torch.float32)
+    _check("ppd_primal_update_vjp", lib().ppd_primal_update_vjp(
+        plan.handle, _ptr(x), _ptr(a), _ptr(b), float(tau), float(eta), float(zeta), float(lam), _ptr(gx_out),
+        _ptr(gxt_out), _ptr(g_x), _ptr(g_a), _ptr(g_b)))
+    return g_x, g_a, g_b
 
 
 class PPDState:

@@ -169,3 +169,73 @@ def test_multichannel_fidelity_gradient():
     A.multichannel_fidelity(plans, xd, ys).backward()
     g = sum(2.0 * op.phit(op.phi(x32.astype(np.float64)) - yc.astype(np.complex128)) for op, yc in zip(ops, yo))
     assert_op_close(host(xd.grad), g, what="multichannel grad")
+
+
+@pytest.mark.parametrize("n_itr", [1, 3])
+def test_dual_update_vjp_matches_oracle_differences(n_itr):
+    """The data-dual update's forward against the oracle's (Algorithm 2 per
+    block, then the generalised Moreau step), and its VJP kernels against
+    FP64 central differences of the oracle's update along random directions
+    of g, v, z and y (blocks away from the ball boundary: smooth)."""
+    P = require_gpu()
+    import torch
+    from oracle import prox as oprox
+    announce(f"dual update VJP n_itr={n_itr}")
+    n, M, d = 64, 6000, 3
+    x, wu, wv, off = synth.small_case(n, M, seed=36, d=d)
+    plan = P.Plan(n, n, wu, wv, off)
+    perm = plan.permutation()
+    rng = np.random.default_rng(12)
+
+    def cplx(k, s=1.0):
+        return s * (rng.standard_normal(k) + 1j * rng.standard_normal(k))
+    y = cplx(M).astype(np.complex64).astype(np.complex128)
+    g = cplx(M, 0.5).astype(np.complex64).astype(np.complex128)
+    v = cplx(M, 0.2).astype(np.complex64).astype(np.complex128)
+    z = y + cplx(M, 0.1)
+    U = np.exp(rng.uniform(np.log(0.05), 0.0, M))
+    mu, lam = 1.0, 0.8
+    w0 = v / U + g
+    eps = np.array([0.5, 3.0, 0.7]) * np.array([np.linalg.norm((w0 - y)[off[j]:off[j + 1]]) for j in range(d)])
+
+    def oracle(g, v, z, y):
+        w = v / U + g
+        zn = np.empty_like(z)
+        for j in range(d):
+            s = slice(off[j], off[j + 1])
+            zn[s] = oprox.fb_ellipsoid(w[s], y[s], eps[j], U[s], mu, n_itr, z[s])
+        return v + lam * (U * (w - zn) - v), zn
+
+    vo, zo = oracle(g, v, z, y)
+    dg = lambda a, dt: dev(a[perm].astype(dt), getattr(torch, dt.__name__))
+    gd, vd, yd = dg(g, np.complex64), dg(v, np.complex64), dg(y, np.complex64)
+    zd, Ud = dev(z[perm], torch.complex128), dev(U[perm], torch.float64)
+    v1, z1, zs = P.ppd_dual_update(plan, gd, yd, Ud, eps, vd, zd, n_itr, mu, lam, keep=True)
+    assert_op_close(host(v1), vo[perm], what="v'")
+    assert_op_close(host(z1), zo[perm], what="z'")
+    # L = Re <a, v'> + Re <b, z'>: its gradients from the VJP kernels
+    a, b = cplx(M), cplx(M)
+    g_g, g_v, g_z, g_y = P.ppd_dual_update_vjp(plan, gd, yd, Ud, eps, vd, zd, n_itr, mu, lam, zs,
+                                               dev(a[perm].astype(np.complex64), torch.complex64),
+                                               dev(b[perm], torch.complex128))
+    grads = {}
+    for name, t in (("g", g_g), ("v", g_v), ("z", g_z), ("y", g_y)):
+        gu = np.empty(M, np.complex128)
+        gu[perm] = host(t)
+        grads[name] = gu
+    a64 = a.astype(np.complex64).astype(np.complex128)
+
+    def L(g_, v_, z_, y_):
+        vv, zz = oracle(g_, v_, z_, y_)
+        return float(np.sum((a64.conj() * vv).real) + np.sum((b.conj() * zz).real))
+    h = 1e-6
+    for name in ("g", "v", "z", "y"):
+        dirn = cplx(M)
+        dirn /= np.linalg.norm(dirn)
+        args_p = dict(g_=g, v_=v, z_=z, y_=y)
+        args_m = dict(args_p)
+        args_p[name + "_"] = args_p[name + "_"] + h * dirn
+        args_m[name + "_"] = args_m[name + "_"] - h * dirn
+        fd = (L(**args_p) - L(**args_m)) / (2 * h)
+        ad = float(np.sum(grads[name].real * dirn.real + grads[name].imag * dirn.imag))
+        assert abs(ad - fd) <= 1e-5 * np.linalg.norm(grads[name]) + 1e-6 * abs(fd), (name, ad, fd)

@@ -6,6 +6,9 @@ defaults (8 x 8 tiles, 128-point items), one Algorithm 2 step per iteration.
   replayed from a HIP graph, element by element against the FP64 oracle
   (Algorithm 3), with the statistics of every iteration against the
   oracle's records.
+* The error of every result against the FP64 oracle, reported per result
+  (Phi, Phi^H, SARA analysis and synthesis, and x, x~, v, z, u, SNR after
+  two iterations of the fused and of the plain per-block FP64 form).
 * 200 iterations (the length the reconstruction SNR bar is stated for)
   against the oracle's stored trajectory (tests/golden/make_ppd512.py): SNR
   within 0.05 dB every 25 iterations, eagerly and replayed from a graph,
@@ -93,3 +96,59 @@ def test_ppd512_200_iterations_vs_oracle_trajectory(graph):
     with torch.cuda.stream(stream):
         plan = P.Plan(n, n, inp.wu[0], inp.wv[0], inp.block_off, stream=stream)
         check_trajectory(P, plan, pb, plan.permutation(), ref, graph, f"ppd512 graph={graph}")
+
+
+def test_ppd512_precision_report():
+    """Relative (norm) and peak-relative error of each result against the
+    FP64 oracle at the benchmark's size, printed as one table; every entry
+    within the parity bar (1e-5; u against its coefficient scale)."""
+    P = require_gpu()
+    import torch
+    announce("ppd512 precision report")
+    inp, pb = _problem()
+    n = inp.workload.n
+    eta = 1.0 / oprob.power_norm(pb.op, pb.U, inp.power_start, tol=1e-3, max_iter=10)
+    rows = []
+
+    def row(name, gpu, ref, bar=1e-5, scale=None):
+        g, r = np.asarray(gpu, np.complex128 if np.iscomplexobj(gpu) else np.float64), np.asarray(ref)
+        rel = float(np.linalg.norm((g - r).ravel()) / max(np.linalg.norm(r.ravel()), 1e-300))
+        peak = float(np.abs(g - r).max() / (scale if scale is not None else max(np.abs(r).max(), 1e-300)))
+        rows.append((name, rel, peak))
+        assert peak <= bar and (scale is not None or rel <= bar), (name, rel, peak)
+
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = P.Plan(n, n, inp.wu[0], inp.wv[0], inp.block_off, stream=stream)
+        perm = plan.permutation()
+        x32 = pb.x_true.astype(np.float32)
+        yg = host(P.ppd_phi(plan, dev(x32, torch.float32)))
+        row("Phi x", yg, pb.op.phi(x32.astype(np.float64))[perm])
+        y32 = pb.y.astype(np.complex64)
+        yd = dev(y32[perm], torch.complex64)
+        row("Phi^H y", host(P.ppd_phit(plan, yd)), pb.op.phit(y32.astype(np.complex128)))
+        c = host(P.ppd_sara(plan, P.SARA_ANALYSIS, dev(x32, torch.float32)))
+        row("Psi^H x", c, osara.analysis(x32.astype(np.float64)))
+        row("Psi c", host(P.ppd_sara(plan, P.SARA_SYNTHESIS, dev(c, torch.float32))),
+            osara.synthesis(c.astype(np.float64)))
+        U = dev(pb.U[perm], torch.float64)
+        xt_dev = dev(x32, torch.float32)
+        ost = O.init_state(n, n, pb.y)
+        recs = O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, O.Params(eta=eta, mu=1.0), ost, 2,
+                         x_true=pb.x_true)
+        u_scale = np.abs(osara.analysis(ost.xt)).max()
+        for form, fname in ((P.FORM_FUSED, "fused"), (P.FORM_PLAIN, "plain")):
+            st = P.PPDState(plan, yd)
+            s = P.ppd_iterate(plan, st, yd, U, pb.eps, 2, eta=eta, mu=1.0, form=form, x_true=xt_dev)
+            stream.synchronize()
+            row(f"x ({fname})", host(st.x), ost.x)
+            row(f"x~ ({fname})", host(st.xt), ost.xt)
+            row(f"v ({fname})", host(st.v), ost.v[perm])
+            row(f"z ({fname})", host(st.z), ost.z[perm])
+            row(f"u ({fname}, peak over coefficient scale)", host(st.u), ost.u, scale=u_scale)
+            d_snr = abs(s["snr_db"] - recs[-1]["snr"])
+            rows.append((f"SNR dB ({fname}, absolute)", d_snr, d_snr))
+            assert d_snr <= 0.05
+    lines = [f"{name:42s} {rel:10.2e} {peak:10.2e}" for name, rel, peak in rows]
+    print("[precision] ppd512, error against the FP64 oracle (relative norm, peak-relative):\n" +
+          "\n".join(lines), flush=True)
