@@ -21,12 +21,18 @@ namespace {
 // workgroup j sums block j's segment partials (one pass of 1024 threads
 // over up to 8192 segments, fixed order), or takes the plain form's sum.
 constexpr int STAT_THREADS = 1024, STAT_PER = 8;
+// The statistics of a call go to out, or with a cursor to row *cursor of a
+// history with rows of `stride` doubles (k_stats advances the cursor), so
+// that a captured graph can write a new row at every replay.
 __global__ __launch_bounds__(STAT_THREADS) void k_stats_resid(const double* __restrict__ rpart,
                                                               const int32_t* __restrict__ bids,
                                                               const int32_t* __restrict__ boff,
                                                               const double* __restrict__ res_sq, int use_res_sq,
-                                                              double* __restrict__ out) {
+                                                              double* __restrict__ out_base,
+                                                              const int32_t* __restrict__ cursor, int stride,
+                                                              double* __restrict__ rj) {
   __shared__ double red[STAT_THREADS / 64];
+  double* out = out_base + (cursor ? size_t(*cursor) * stride : 0);
   const int j = blockIdx.x;
   double r2 = 0.0;
   if (use_res_sq) {
@@ -49,15 +55,21 @@ __global__ __launch_bounds__(STAT_THREADS) void k_stats_resid(const double* __re
     r2 = 0.0;
     for (int q = 0; q < STAT_THREADS / 64; ++q) r2 += red[q];
   }
-  if (threadIdx.x == 0) out[8 + j] = sqrt(r2);
+  if (threadIdx.x == 0) {
+    out[8 + j] = sqrt(r2);
+    rj[j] = sqrt(r2);   // a device copy for k_stats (out may be host memory)
+  }
 }
 
 // out: [0] rel change, [1] ||x||, [2] SNR dB, [3] max_j r_j / eps_j,
 //      [4..7] raw sums, [8 + j] r_j (from k_stats_resid).
 __global__ __launch_bounds__(256) void k_stats(const double* __restrict__ ppart, int nparts,
                                                const double* __restrict__ eps, int d, int has_truth,
-                                               double* __restrict__ out) {
+                                               double* __restrict__ out_base, int32_t* __restrict__ cursor,
+                                               int stride, const uint32_t* __restrict__ flag,
+                                               const double* __restrict__ rj) {
   __shared__ double red[4][4];
+  double* out = out_base + (cursor ? size_t(*cursor) * stride : 0);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < nparts; i += 256)
     for (int k = 0; k < 4; ++k) s[k] += ppart[4 * i + k];
@@ -69,7 +81,7 @@ __global__ __launch_bounds__(256) void k_stats(const double* __restrict__ ppart,
   if (threadIdx.x == 0) {
     for (int k = 0; k < 4; ++k) s[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
     double rmax = 0.0;
-    for (int j = 0; j < d; ++j) rmax = fmax(rmax, out[8 + j] / eps[j]);
+    for (int j = 0; j < d; ++j) rmax = fmax(rmax, rj[j] / eps[j]);
     // ||x_t - x_{t-1}|| / ||x_t||, 0 when both vanish (an all-zero iterate)
     out[0] = sqrt(s[0]) / fmax(sqrt(s[1]), 1e-300);
     out[1] = sqrt(s[1]);
@@ -79,8 +91,12 @@ __global__ __launch_bounds__(256) void k_stats(const double* __restrict__ ppart,
     out[5] = s[1];
     out[6] = s[2];
     out[7] = s[3];
+    if (cursor) *cursor += 1;
+    if (flag) out[8 + d] = double(*flag);   // the persistent barrier's give-up flag, read back with them
   }
 }
+
+__global__ void k_set_i32(int32_t* __restrict__ a, int32_t v) { *a = v; }
 
 __global__ void k_img_norm2(const float* __restrict__ a, int64_t n, double* __restrict__ part) {
   double s = 0.0;
@@ -154,6 +170,11 @@ struct IterCtx {
   bool persistent;    // Algorithm 2 middle steps in one persistent launch
   int spin_limit;     // its grid-barrier bound (0: default)
   hipEvent_t sara_done = nullptr;   // the persistent launch waits for the SARA branch
+  // statistics reduced right after the iteration (captured graphs): into
+  // stats_out, at the plan's history cursor if stats_cursor
+  double* stats_out = nullptr;
+  bool stats_cursor = false;
+  int has_truth = 0, use_res_sq = 0;
 };
 
 // Runs the plan's launches on another stream for the lifetime of the object.
@@ -247,14 +268,15 @@ int one_iteration(ppd_plan* p, const IterCtx& c) {
 }
 
 std::string graph_key(const IterCtx& c) {
-  char buf[600];
-  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d %d %d %d %d",
+  char buf[700];
+  std::snprintf(buf, sizeof(buf), "%p %p %p %p %p %p %p %p %p %p %p %p %p %p %a %a %a %a %a %a %a %d %d %d %d %d %d %p %d %d %d",
                 (void*)c.dual.y, (void*)c.dual.U, (void*)c.dual.v, (void*)c.dual.z, (void*)c.primal.x,
                 (void*)c.primal.xt, (void*)c.primal.x_true, (void*)c.u, (void*)c.primal.ut, (void*)c.W,
                 (const void*)c.dual.active, (const void*)c.basis_active, (const void*)c.primal.part, (const void*)c.dual.rpart,
                 c.dual.mu,
                 c.dual.lambda, c.primal.tau, c.primal.eta, c.primal.zeta, double(c.alpha),
-                double(c.lambda), c.dual.n_itr, c.form, c.prox, c.n_newton, int(c.persistent), c.spin_limit);
+                double(c.lambda), c.dual.n_itr, c.form, c.prox, c.n_newton, int(c.persistent), c.spin_limit,
+                (void*)c.stats_out, int(c.stats_cursor), c.has_truth, c.use_res_sq);
   return std::string(buf);
 }
 
@@ -270,7 +292,10 @@ int iteration_graph(ppd_plan* p, const IterCtx& c, int slot, hipGraphExec_t* out
     p->graph[slot] = nullptr;
     p->graph_key[slot].clear();
     PPD_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-    const int cst = one_iteration(p, c);
+    int cst = one_iteration(p, c);
+    if (cst == PPD_OK && c.stats_out)
+      cst = stats_finalize(p, c.has_truth, c.use_res_sq, c.stats_out, c.stats_cursor ? p->hist_cursor : nullptr,
+                           8 + p->d);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(p->stream, &g);
     if (cst != PPD_OK) {
@@ -288,13 +313,13 @@ int iteration_graph(ppd_plan* p, const IterCtx& c, int slot, hipGraphExec_t* out
 
 }  // namespace
 
-int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq, double* out) {
+int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq, double* out, int32_t* cursor, int stride) {
   int slot;
   PPD_TRY(timer_begin(p, KK_STATS, &slot));
   hipLaunchKernelGGL(k_stats_resid, dim3(p->d), dim3(STAT_THREADS), 0, p->stream, p->rpart, p->bseg_ids,
-                     p->bseg_off_d, p->res_sq, use_res_sq, out);
+                     p->bseg_off_d, p->res_sq, use_res_sq, out, cursor, stride, p->rj_d);
   hipLaunchKernelGGL(k_stats, dim3(1), dim3(256), 0, p->stream, p->ppart, primal_partial_count(p), p->eps_d, p->d,
-                     has_truth, out);
+                     has_truth, out, cursor, stride, out == p->host_stats_dev ? p->pa_sync + 2 : nullptr, p->rj_d);
   PPD_HIP(hipGetLastError());
   return timer_end(p, slot);
 }
@@ -355,7 +380,7 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   auto periodic = [&](int done) -> int {
     if (every <= 0 || done % every) return PPD_OK;
     double* out = prm->stats_history ? prm->stats_history + size_t(done / every - 1) * (8 + p->d) : p->stats_d;
-    return stats_finalize(p, prm->x_true != nullptr, prm->form == PPD_FORM_PLAIN, out);
+    return stats_finalize(p, prm->x_true != nullptr, prm->form == PPD_FORM_PLAIN, out, nullptr, 0);
   };
   c.u = st->u;
   c.W = prm->W;
@@ -379,17 +404,29 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
     // the next one's
     PPD_TRY(fft_rows_forward(p, st->xt, p->half_f));
     if (prm->use_graph) {
-      // two captured iterations: slot 1 forms the statistics partials (the
-      // iterations whose statistics are reduced), slot 0 does not
-      IterCtx c0 = c;
+      // three captured iterations: slot 0 without statistics partials,
+      // slot 1 with them and the periodic reduction (into the next history
+      // row at the plan's cursor, or the plan's buffer), slot 2 with the
+      // partials only (the call's last iteration, reduced after the loop)
+      IterCtx c0 = c, c1 = c;
       c0.primal.part = nullptr;
       c0.dual.rpart = nullptr;
+      c1.has_truth = prm->x_true != nullptr;
+      c1.use_res_sq = prm->form == PPD_FORM_PLAIN;
+      c1.stats_cursor = prm->stats_history != nullptr;
+      c1.stats_out = prm->stats_history ? prm->stats_history : p->stats_d;
+      if (every > 0 && prm->stats_history) {
+        hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, p->stream, p->hist_cursor, 0);
+        PPD_HIP(hipGetLastError());
+      }
       for (int t = 0; t < n_iter; ++t) {
-        const bool read = (t + 1 == n_iter && (stats || residual)) || (every > 0 && (t + 1) % every == 0);
+        const bool periodic_t = every > 0 && (t + 1) % every == 0;
+        const bool last_read = t + 1 == n_iter && (stats || residual);
         hipGraphExec_t ex = nullptr;
-        PPD_TRY(iteration_graph(p, read ? c : c0, read && c.primal.part ? 1 : 0, &ex));
+        if (periodic_t) PPD_TRY(iteration_graph(p, c1, 1, &ex));
+        else if (last_read) PPD_TRY(iteration_graph(p, c, 2, &ex));
+        else PPD_TRY(iteration_graph(p, c0, 0, &ex));
         PPD_HIP(hipGraphLaunch(ex, p->stream));
-        PPD_TRY(periodic(t + 1));
       }
     } else {
       for (int t = 0; t < n_iter; ++t) {
@@ -407,12 +444,12 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
   }
   if (stats || residual) {
     if (n_iter == 0) return fail(PPD_EINVAL, "ppd_iterate: statistics need n_iter >= 1");
-    PPD_TRY(stats_finalize(p, prm->x_true != nullptr, prm->form == PPD_FORM_PLAIN, p->stats_d));
-    std::vector<double> h(8 + p->d);
-    uint32_t gave_up = 0;
-    PPD_HIP(hipMemcpyAsync(h.data(), p->stats_d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, p->stream));
-    PPD_HIP(hipMemcpyAsync(&gave_up, p->pa_sync + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, p->stream));
+    // the reduction writes the statistics and the give-up flag straight into
+    // mapped pinned host memory: one synchronisation, no copy
+    PPD_TRY(stats_finalize(p, prm->x_true != nullptr, prm->form == PPD_FORM_PLAIN, p->host_stats_dev, nullptr, 0));
     PPD_HIP(hipStreamSynchronize(p->stream));
+    const double* h = p->host_stats;
+    const bool gave_up = h[8 + p->d] != 0.0;
     if (gave_up) {
       // a grid barrier of the persistent launch gave up waiting (this call
       // or an earlier one without statistics): its results are not valid

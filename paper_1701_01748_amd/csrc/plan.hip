@@ -214,10 +214,11 @@ static int dalloc(ppd_plan* p, T** ptr, size_t count) {
 static void destroy_plan(ppd_plan* p) {
   if (!p) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
     if (p->graph_exec[k]) (void)hipGraphExecDestroy(p->graph_exec[k]);
     if (p->graph[k]) (void)hipGraphDestroy(p->graph[k]);
   }
+  if (p->host_stats) (void)hipHostFree(p->host_stats);
   if (p->aux) (void)hipStreamSynchronize(p->aux);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
@@ -612,6 +613,8 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   A(dalloc(p, &p->eps_d, p->d));
   A(dalloc(p, &p->ppart, size_t(p->ny) * 4));
   A(dalloc(p, &p->stats_d, 8 + p->d));
+  A(dalloc(p, &p->hist_cursor, 1));
+  A(dalloc(p, &p->rj_d, p->d));
   // SARA temporaries: low-pass bands of levels 1..L-1 for 8 wavelet bases
   size_t ll = 0;
   for (int l = 1; l < levels; ++l) ll += N >> (2 * l);
@@ -673,6 +676,12 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   if (st == PPD_OK) {
     p->pa_ok = pa_fits && p->pa_groups <= alg2_persistent_capacity();
   }
+  // mapped pinned host memory the final statistics reduction writes into
+  if (st == PPD_OK && (hipHostMalloc(reinterpret_cast<void**>(&p->host_stats), sizeof(double) * (9 + p->d),
+                                     hipHostMallocMapped) != hipSuccess ||
+                       hipHostGetDevicePointer(reinterpret_cast<void**>(&p->host_stats_dev), p->host_stats, 0) !=
+                           hipSuccess))
+    st = fail(PPD_ENOMEM, "mapped pinned memory for the statistics read-back failed");
   // default priority on purpose: both streams of an iteration are equal
   if (st == PPD_OK && (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
                        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -716,7 +725,7 @@ int ppd_plan_destroy(ppd_plan* plan) {
 
 int ppd_plan_set_stream(ppd_plan* plan, void* stream) {
   if (!plan) return fail(PPD_EINVAL, "NULL plan");
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
     if (plan->graph_exec[k]) (void)hipGraphExecDestroy(plan->graph_exec[k]);
     if (plan->graph[k]) (void)hipGraphDestroy(plan->graph[k]);
     plan->graph_exec[k] = nullptr;

@@ -177,6 +177,10 @@ struct ppd_plan {
   std::vector<double> eps_cache;
   double* ppart = nullptr;                 // [ny][4] primal statistics partials
   double* stats_d = nullptr;               // [8 + d]
+  int32_t* hist_cursor = nullptr;          // [1] next statistics history row of a graph replay
+  double* rj_d = nullptr;                  // [d] block residuals of the last statistics reduction
+  double* host_stats = nullptr;            // pinned host [8 + d + 1]: a call's statistics and give-up flag
+  double* host_stats_dev = nullptr;        // its device-side address
   float* sara_ll = nullptr;                // LL temporaries, analysis
   float* sara_rec = nullptr;               // reconstruction temporaries
   float* ut = nullptr;                     // [ny][nx] Psi u
@@ -196,11 +200,11 @@ struct ppd_plan {
   size_t ws_bytes = 0, ws_used = 0;
   bool ws_measure = false;
 
-  // graph replay of one iteration: slot 0 without, slot 1 with the
-  // statistics partials
-  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  std::string graph_key[2];
+  // graph replay of one iteration: slot 0 without the statistics partials,
+  // slot 1 with them and the periodic reduction, slot 2 with them only
+  hipGraphExec_t graph_exec[3] = {nullptr, nullptr, nullptr};
+  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+  std::string graph_key[3];
 
   // optional per-launch timing
   bool timing = false;
@@ -269,7 +273,8 @@ int sara_dual(ppd_plan* p, const float* x, float* u, float alpha, float lambda, 
               const uint8_t* active = nullptr);   // active: DEVICE [9] basis mask, NULL = all
 int sara_synthesis(ppd_plan* p, const float* u, float* out, const float* W);
 
-int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq, double* out);   // out: [8 + d]
+// out: [8 + d], or with a cursor row *cursor of rows of `stride` doubles (advanced)
+int stats_finalize(ppd_plan* p, int has_truth, int use_res_sq, double* out, int32_t* cursor, int stride);
 int upload_eps(ppd_plan* p, const double* eps_host);
 
 // host-side setup helpers
