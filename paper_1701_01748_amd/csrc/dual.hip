@@ -473,7 +473,7 @@ __global__ void k_pl_w(int64_t b0, int64_t b1, const float2* __restrict__ v, con
   for (int64_t i = b0 + blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < b1; i += int64_t(gridDim.x) * blockDim.x) {
     const float2 ve = v[i], g = yhat[i], ye = y[i];
     const double Ue = U[i];
-    w[i] = make_double2(double(ve.x) / Ue + double(g.x), double(ve.y) / Ue + double(g.y));
+    w[i] = dual_arg(ve, Ue, g);
     const double ex = double(g.x) - double(ye.x), ey = double(g.y) - double(ye.y);
     rn += ex * ex + ey * ey;
   }

@@ -514,11 +514,11 @@ __global__ __launch_bounds__(GridCfg<T>::THREADS) void k_grid(
 // its 8 taps), wx_k(j) likewise along u: a 16 x 16 x K product of the
 // separable weights, accumulated over the item's visibilities 4 at a time by
 // v_mfma_f32_16x16x4_f32 (real and imaginary parts), in FP32 registers.  A
-// batch of 64 visibilities is prepared one per lane, as in k_grid, and
-// written to LDS as zero-padded 16-entry weight rows (the A operand) and
-// value-scaled weight rows (B), 32 rows at a time; lane l of a product step
-// then reads row 4 g + l / 16, entry l mod 16, of each.  No read-modify-write
-// of LDS.
+// batch of 64 visibilities is prepared one per lane, as in k_grid, and its
+// taps are written into 16-entry LDS rows that are zero elsewhere: weight
+// rows (the A operand) and value-scaled weight rows (B), 32 rows at a time;
+// lane l of a product step then reads row 4 g + l / 16, entry l mod 16, of
+// each.  No read-modify-write of LDS.
 //
 // An 8 x 8 tile holds about one batch, so a single-wave workgroup takes a
 // run of consecutive items, and the wave's (item, batch) steps form one
@@ -744,10 +744,39 @@ __global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
   grid_load<DUAL>(src, tabs[0], total, lane, 0, sb, bn);
   float* arow = sA + (lane & 31) * GM_AS;
   float2* brow = sB + (lane & 31) * GM_BS;
+  const float* aq = sA + gq * GM_AS + gc;    // entry read by this lane in product step 0
+  const float2* bq = sB + gq * GM_BS + gc;
+  // the staging rows start zero; each batch writes its taps and clears them
+  for (int e = lane; e < 32 * GM_AS; e += 64) sA[e] = 0.f;
+  for (int e = lane; e < 32 * GM_BS; e += 64) sB[e] = make_float2(0.f, 0.f);
+  __builtin_amdgcn_wave_barrier();
   while (true) {
-    const GridBatch bt = bn;
     const int nb = min(64, total - kb * 64);
     const int c0 = field(itl.tx, cur) * T, r0 = field(itl.ty, cur) * T;
+    // this step's taps and values, from the operands loaded during the
+    // previous step; bn is free again afterwards
+    double2 znew{};
+    float2 vnew{};
+    float vx = 0.f, vy = 0.f;
+    Taps t;
+    t.ou = 0;
+    t.ov = 0;
+    const bool has = lane < nb;
+    const int pi = bn.pi;
+    const bool zst = DUAL && has && bn.act;
+    if (has) {
+      taps_for<T>(bn.ou, bn.ov, su, sv, Kx, Ky, c0, r0, kbw.c, t);
+      const float2 val = grid_value<DUAL>(bn, mu, lambda, exact, znew, vnew);
+      vx = val.x * bn.th;
+      vy = val.y * bn.th;
+    }
+    // stores before the next step's loads: vector memory operations
+    // complete in issue order, so the wait for those loads does not add a
+    // wait for stores issued after them
+    if (zst) {
+      z[pi] = znew;
+      v[pi] = vnew;
+    }
     // the next step: the next batch of this item, else the next item's first
     const bool last = (kb + 1) * 64 >= total;
     const int nxt = last ? cur + 1 : cur;
@@ -763,64 +792,55 @@ __global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
       }
       grid_load<DUAL>(src, tn, ntotal, lane, last ? 0 : kb + 1, sb, bn);
     }
-    double2 znew{};
-    float2 vnew{};
-    float vx = 0.f, vy = 0.f;
-    Taps t;
-    if (lane < nb) {
-      taps_for<T>(bt.ou, bt.ov, su, sv, Kx, Ky, c0, r0, kbw.c, t);
-      const float2 val = grid_value<DUAL>(bt, mu, lambda, exact, znew, vnew);
-      vx = val.x * bt.th;
-      vy = val.y * bt.th;
-    } else {
-      // rows past the batch end are read by its last product step: all zero
-      t.ou = 0;
-      t.ov = 0;
-#pragma unroll
-      for (int m = 0; m < KB_TAPS; ++m) {
-        t.wx[m] = 0.f;
-        t.wy[m] = 0.f;
-      }
-    }
     // The batch goes through LDS in two halves of 32 rows (half the staging
-    // memory: more waves per CU): lanes 0-31 write their rows and the first
-    // 8 product steps read them, then lanes 32-63.  Each lane writes the 8
-    // taps at the footprint offset and zeros in the 8 other entries.
+    // memory: more waves per CU): lanes 0-31 write their 8 taps into rows
+    // that are otherwise zero and the first 8 product steps read them, the
+    // lanes put the zeros back, then the same for lanes 32-63.  Rows of
+    // lanes past the batch end are never written.  The tap stores go to a
+    // per-lane base with constant offsets; LDS operations of one wave take
+    // effect in program order, so the zeros land after the product reads.
+    float* pa = arow + t.ov;
+    float2* pb = brow + t.ou;
     for (int h = 0; h * 32 < nb; ++h) {
-      if ((lane >> 5) == h) {
+      const bool mine = has && (lane >> 5) == h;
+      if (mine) {
 #pragma unroll
         for (int m = 0; m < KB_TAPS; ++m) {
-          arow[t.ov + m] = t.wy[m];
-          arow[(t.ov + KB_TAPS + m) & 15] = 0.f;
-          brow[t.ou + m] = make_float2(t.wx[m] * vx, t.wx[m] * vy);
-          brow[(t.ou + KB_TAPS + m) & 15] = make_float2(0.f, 0.f);
+          pa[m] = t.wy[m];
+          pb[m] = make_float2(t.wx[m] * vx, t.wx[m] * vy);
         }
       }
       __builtin_amdgcn_wave_barrier();
-      // two accumulator pairs (even / odd product steps): independent chains
-      const int ng = (min(32, nb - 32 * h) + 3) >> 2;
-      int g = 0;
-      for (; g + 2 <= ng; g += 2) {
-        const int ra = 4 * g + gq, rb = ra + 4;
-        const float a0 = sA[ra * GM_AS + gc], a1 = sA[rb * GM_AS + gc];
-        const float2 b0 = sB[ra * GM_BS + gc], b1 = sB[rb * GM_BS + gc];
-        accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.x, accr, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.y, acci, 0, 0, 0);
-        accr2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1.x, accr2, 0, 0, 0);
-        acci2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1.y, acci2, 0, 0, 0);
+      // all 8 steps' operands in one go (rows past the batch end read as
+      // zero), then the products; two accumulator pairs (even / odd steps)
+      // make independent chains
+      float a8[8];
+      float2 b8[8];
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        a8[g] = aq[4 * g * GM_AS];
+        b8[g] = bq[4 * g * GM_BS];
       }
-      if (g < ng) {
-        const int ra = 4 * g + gq;
-        const float a0 = sA[ra * GM_AS + gc];
-        const float2 b0 = sB[ra * GM_BS + gc];
-        accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.x, accr, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0.y, acci, 0, 0, 0);
+      const int ng = (min(32, nb - 32 * h) + 3) >> 2;
+#pragma unroll
+      for (int g = 0; g < 8; g += 2) {
+        if (g < ng) {
+          accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g], b8[g].x, accr, 0, 0, 0);
+          acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g], b8[g].y, acci, 0, 0, 0);
+        }
+        if (g + 1 < ng) {
+          accr2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g + 1], b8[g + 1].x, accr2, 0, 0, 0);
+          acci2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g + 1], b8[g + 1].y, acci2, 0, 0, 0);
+        }
       }
       __builtin_amdgcn_wave_barrier();
-    }
-    if (DUAL && lane < nb && bt.act) {
-      z[bt.pi] = znew;
-      v[bt.pi] = vnew;
+      if (mine) {
+#pragma unroll
+        for (int m = 0; m < KB_TAPS; ++m) {
+          pa[m] = 0.f;
+          pb[m] = make_float2(0.f, 0.f);
+        }
+      }
     }
     if (last) {
       // Lane l holds rows 4 (l / 16) + e, e = 0..3, of column l mod 16 (row

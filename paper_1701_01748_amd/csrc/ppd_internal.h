@@ -315,7 +315,8 @@ static_assert(KB_DEG % 2 == 1, "even / odd split assumes an odd degree");
 // stores Theta G a (complex64) and rebuilds w where it is needed, bitwise
 // the same each time.
 __device__ __forceinline__ double2 dual_arg(float2 v, double U, float2 ga) {
-  return make_double2(double(v.x) / U + double(ga.x), double(v.y) / U + double(ga.y));
+  const double r = 1.0 / U;   // one division per visibility, shared by both parts
+  return make_double2(double(v.x) * r + double(ga.x), double(v.y) * r + double(ga.y));
 }
 
 // Segment table of a work item in LDS: the offsets of its segments in the

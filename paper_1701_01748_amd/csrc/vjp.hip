@@ -37,7 +37,7 @@ struct DuIn {
 // w = U^-1 v + g in FP64 (the argument of the generalised Moreau step)
 __device__ __forceinline__ double2 du_w(const DuIn& a, int64_t i, double Ue) {
   const float2 ve = a.v[i], ge = a.g[i];
-  return make_double2(double(ve.x) / Ue + double(ge.x), double(ve.y) / Ue + double(ge.y));
+  return dual_arg(ve, Ue, ge);
 }
 
 // Chunk partials of ||q - y||^2 (and, with gz, of Re <q - y, gz>) for
