@@ -22,6 +22,10 @@ namespace {
 // Elements per thread of a staging pass: every launch below has at most
 // 4 * blockDim.x of them (checked on the host).
 constexpr int FFT_PER = 4;
+// Columns per workgroup of the column passes (at most 4096 / L).
+#ifndef PPD_FFT_COLS
+#define PPD_FFT_COLS 16
+#endif
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }
 __host__ __device__ inline int padded_len(int L) { return L + (L >> 5) + 1; }
@@ -223,8 +227,10 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// Inverse rows: half rows -> image rows.  PRIMAL fuses Algorithm 3 steps
-// 28-30 and the FP64 statistics partials of the new iterate; NEXT also runs
+// Inverse rows: half rows -> image rows.  PRIMAL fuses the primal update of
+// Algorithm 3 (gradient step, projection onto the positive orthant,
+// relaxation and the extrapolated iterate) and the FP64 statistics partials
+// of the new iterate; NEXT also runs
 // the forward row pass of the new x~ (the first transform of the next
 // iteration's F Z x~) on the rows just updated, into half_next.
 template <bool PRIMAL, bool NEXT>
@@ -341,7 +347,7 @@ RowCfg row_cfg(int L, int rows) {
 
 ColCfg col_cfg(int L, int Kx) {
   ColCfg c;
-  c.C = std::max(1, std::min(16, 4096 / L));
+  c.C = std::max(1, std::min(PPD_FFT_COLS, 4096 / L));
   c.C = std::min(c.C, Kx);
   c.threads = std::min(1024, std::max(64, c.C * L / 4));
   c.ngroups = Kx / c.C;
