@@ -811,26 +811,31 @@ __global__ __launch_bounds__(64 * PPD_GRIDM_WPG) void k_grid_mfma(
         }
       }
       __builtin_amdgcn_wave_barrier();
-      // all 8 steps' operands in one go (rows past the batch end read as
-      // zero), then the products; two accumulator pairs (even / odd steps)
-      // make independent chains
-      float a8[8];
-      float2 b8[8];
-#pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        a8[g] = aq[4 * g * GM_AS];
-        b8[g] = bq[4 * g * GM_BS];
-      }
+      // the operands of PPD_GRIDM_READ_AHEAD product steps are read before
+      // their first product (rows past the batch end read as zero); two
+      // accumulator pairs (even / odd steps) make independent chains
+      constexpr int RA = PPD_GRIDM_READ_AHEAD;
+      static_assert(RA == 2 || RA == 4 || RA == 8, "read-ahead of 2, 4 or 8 product steps");
       const int ng = (min(32, nb - 32 * h) + 3) >> 2;
 #pragma unroll
-      for (int g = 0; g < 8; g += 2) {
-        if (g < ng) {
-          accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g], b8[g].x, accr, 0, 0, 0);
-          acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g], b8[g].y, acci, 0, 0, 0);
+      for (int g0 = 0; g0 < 8; g0 += RA) {
+        float a8[RA];
+        float2 b8[RA];
+#pragma unroll
+        for (int g = 0; g < RA; ++g) {
+          a8[g] = aq[4 * (g0 + g) * GM_AS];
+          b8[g] = bq[4 * (g0 + g) * GM_BS];
         }
-        if (g + 1 < ng) {
-          accr2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g + 1], b8[g + 1].x, accr2, 0, 0, 0);
-          acci2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g + 1], b8[g + 1].y, acci2, 0, 0, 0);
+#pragma unroll
+        for (int g = 0; g < RA; g += 2) {
+          if (g0 + g < ng) {
+            accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g], b8[g].x, accr, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g], b8[g].y, acci, 0, 0, 0);
+          }
+          if (g0 + g + 1 < ng) {
+            accr2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g + 1], b8[g + 1].x, accr2, 0, 0, 0);
+            acci2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a8[g + 1], b8[g + 1].y, acci2, 0, 0, 0);
+          }
         }
       }
       __builtin_amdgcn_wave_barrier();

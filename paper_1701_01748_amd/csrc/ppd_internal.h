@@ -60,6 +60,11 @@ constexpr int FOLD_HEAVY = PPD_FOLD_HEAVY;   // item regions above which a tile'
 #ifndef PPD_GRIDM_WPG
 #define PPD_GRIDM_WPG 1
 #endif
+// Product steps of the matrix-core gridding whose LDS operands are read
+// before the first of their products (2, 4 or 8).
+#ifndef PPD_GRIDM_READ_AHEAD
+#define PPD_GRIDM_READ_AHEAD 2
+#endif
 
 // Launch order of the work items over the XCDs: the items, in spatial
 // order, are cut into 8 contiguous bands of near-equal work (64-point
