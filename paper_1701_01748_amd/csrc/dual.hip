@@ -162,8 +162,7 @@ struct PaArgs {
 };
 
 // Arrivals are counted in two levels, so that no single counter takes
-// every workgroup's atomic (one counter for ~600 workgroups cost ~30 us per
-// barrier): workgroup g counts on sub-counter g mod PA_NSUB, and the
+// every workgroup's atomic: workgroup g counts on sub-counter g mod PA_NSUB, and the
 // workgroup completing a sub-counter's count for this barrier counts on the
 // top counter; waiters poll the top counter.  Counts grow over the launch
 // (barrier s completes a sub-counter at (s + 1) x its members and the top
@@ -177,6 +176,9 @@ struct PaArgs {
 // device-coherent loads.  The wait for all outstanding memory operations
 // makes the exchanges complete (acknowledged) before the arrival is
 // counted.  Returns 1 when every workgroup has arrived, 0 after a give-up.
+#ifndef PPD_PA_SLEEP
+#define PPD_PA_SLEEP 2   // s_sleep argument between polls (units of 64 clocks)
+#endif
 __device__ int grid_barrier(uint32_t* sync, int g, int G, int s, int spin_limit) {
   const int nsub = min(G, PA_NSUB);
   const int sub = g % nsub;
@@ -203,7 +205,9 @@ __device__ int grid_barrier(uint32_t* sync, int g, int G, int s, int spin_limit)
       ok = 0;
       break;
     }
-    __builtin_amdgcn_s_sleep(2);
+#if PPD_PA_SLEEP > 0
+    __builtin_amdgcn_s_sleep(PPD_PA_SLEEP);
+#endif
   }
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   return ok;

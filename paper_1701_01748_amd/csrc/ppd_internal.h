@@ -38,10 +38,23 @@ constexpr int SEC_CHUNK = 2048;   // points per workgroup of an exact-prox Newto
 constexpr int MAX_ITEM_SEGS = 64; // per-block segments of one work item (one wave scans them)
 constexpr int MAX_XCD = 8;
 constexpr int PA_THREADS = 256;   // persistent Algorithm 2: threads per workgroup
-constexpr int PA_PER = 8;         // points per thread held in registers
+#ifndef PPD_PA_PER
+#define PPD_PA_PER 12
+#endif
+// points per thread held in registers: 12 (230 VGPRs, 2 waves per SIMD)
+// leaves fewer workgroups to meet at each barrier than 8 and still fits
+// the co-residency limit at 1.3M points
+constexpr int PA_PER = PPD_PA_PER;
 constexpr int PA_CHUNK = PA_THREADS * PA_PER;
 constexpr int PA_MAXB = 4;        // data blocks one workgroup's points may span
-constexpr int PA_NSUB = 32;       // sub-counters of its grid barrier
+#ifndef PPD_PA_NSUB
+#define PPD_PA_NSUB 4
+#endif
+// sub-counters of its grid barrier: with 424 workgroups 1, 2, 4, 8, 16 and
+// 32 of them measured 215, 205, 202, 203, 207 and 213 us per iteration
+// with 5 Algorithm 2 steps (one counter takes every arrival; many add a
+// level of contention on the top counter)
+constexpr int PA_NSUB = PPD_PA_NSUB;
 constexpr int PA_SUB0 = 32;       // first sub-counter in the sync array (uint32 index)
 constexpr int PA_SUBSTRIDE = 32;  // one 128-byte line per sub-counter
 constexpr int PA_SYNC_WORDS = PA_SUB0 + PA_SUBSTRIDE * PA_NSUB;
