@@ -266,19 +266,21 @@ typedef struct {
                                       in the fused form and Algorithm 2, the
                                       n_itr - 1 middle steps run as one
                                       persistent launch with the per-point
-                                      state in registers and a bounded grid
-                                      barrier per step, when the plan's
-                                      points fit the device at once (about
-                                      2M visibilities) and no 2048 consecutive
-                                      plan-order points span more than 4
-                                      blocks (the launch waits for the SARA
-                                      branch of its iteration and needs the
-                                      device to itself: work that other
-                                      streams run beside it can make a
-                                      barrier give up); PPD_PERSIST_OFF (1):
-                                      one launch pair per step               */
-  int32_t spin_limit;              /* polls of a persistent grid barrier
-                                      before it gives up (0: 2^20); a give-up
+                                      state in registers and bounded waits
+                                      for each block's partial norms, when
+                                      the plan's points fit the device at
+                                      once (about 1.5M visibilities) and no
+                                      3072 consecutive plan-order points
+                                      span more than 4 blocks (the launch
+                                      waits for the SARA branch of its
+                                      iteration and needs the device to
+                                      itself: work that other streams run
+                                      beside it can make a wait give up);
+                                      PPD_PERSIST_OFF (1): one launch pair
+                                      per step                               */
+  int32_t spin_limit;              /* polls of one wait of the persistent
+                                      launch before it gives up (0: 2^20);
+                                      a give-up
                                       makes every workgroup finish and the
                                       next call that reads statistics return
                                       PPD_EDEVICE                            */

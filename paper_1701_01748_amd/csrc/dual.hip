@@ -139,14 +139,28 @@ __global__ __launch_bounds__(BF_THREADS) void k_block_factors(const double* __re
 // with the per-point state (w, z, U, y) held in registers: workgroup g owns
 // the PA_CHUNK plan-order points from g PA_CHUNK (blocks are contiguous in
 // plan order, so these span at most PA_MAXB blocks; the plan checks it).  A
-// step applies z <- P_B(q) with the block factors, forms the workgroup's
-// partial ||q - y_j||^2 of the next q per block it touches, and meets the
-// other workgroups at a grid barrier; every workgroup of block j then sums
-// the block's workgroup partials in the same fixed order, so all of them
-// get the same factor.  The grid is launched only when all its workgroups
-// fit the device at once.  The barrier's wait is bounded: a workgroup that
-// has polled spin_limit times sets a give-up flag that releases every other
-// waiter, all workgroups run to the end, and the host reports the flag.
+// step applies z <- P_B(q) with the block factors and forms the workgroup's
+// partial ||q - y_j||^2 of the next q per block it touches; every workgroup
+// of block j then sums the block's workgroup partials in the same fixed
+// order, so all of them get the same factor.  The grid is launched only when
+// all its workgroups fit the device at once.
+//
+// There is no grid-wide barrier: a step of block j waits only for the
+// partials of block j's workgroups.  Each partial is published in a slot of
+// its own with one device-scope atomic exchange and carries its step in the
+// sign bit (the partials are sums of squares, so the sign is free): slot
+// s mod 2 of step s holds +p when bit 1 of s is clear and -p when it is set.
+// A reader of step s finds in that slot either step s's partial (ready),
+// step s - 2's (the writer is behind; it can never be ahead, because its
+// step s + 1 needs the reader's own step s + 1 partial) or a NaN left by the
+// previous launch's reset (step 0 and 1), so the sign tells them apart.  The
+// wait is bounded: a thread that has polled spin_limit times sets a give-up
+// flag that every other waiter checks, all workgroups run to the end, and
+// the host reports the flag.  The last workgroup out puts NaN back into
+// every slot for the next launch (the plan starts them at NaN).
+#ifndef PPD_PA_SLEEP
+#define PPD_PA_SLEEP 1   // s_sleep argument between polls (units of 64 clocks)
+#endif
 struct PaArgs {
   int steps, G, d, spin_limit;
   int64_t M;
@@ -157,66 +171,35 @@ struct PaArgs {
   const int32_t* voff; const int32_t* wgb0; const int32_t* gfirst; const int32_t* glast;
   const double* eps;
   double2* bfac;
-  double* part;
-  uint32_t* sync;
+  uint64_t* part;   // [2][G][PA_MAXB] tagged partials
+  uint32_t* sync;   // [1] exits, [2] give-up flag
 };
 
-// Arrivals are counted in two levels, so that no single counter takes
-// every workgroup's atomic: workgroup g counts on sub-counter g mod PA_NSUB, and the
-// workgroup completing a sub-counter's count for this barrier counts on the
-// top counter; waiters poll the top counter.  Counts grow over the launch
-// (barrier s completes a sub-counter at (s + 1) x its members and the top
-// counter at (s + 1) x the sub-counters in use).  sync[0] top, sync[1]
-// exits, sync[2] give-up flag, sync[PA_SUB0 + PA_SUBSTRIDE k] sub-counter k.
-// Called by one thread of the workgroup after it has published the
-// workgroup's partials with atomic exchanges.  No cache-wide write-back or
-// invalidate is used (one per workgroup and barrier cost ~50 us per step):
-// everything the barrier publishes goes through device-scope atomics,
-// which are performed at the device's coherence point, and is read with
-// device-coherent loads.  The wait for all outstanding memory operations
-// makes the exchanges complete (acknowledged) before the arrival is
-// counted.  Returns 1 when every workgroup has arrived, 0 after a give-up.
-#ifndef PPD_PA_SLEEP
-#define PPD_PA_SLEEP 2   // s_sleep argument between polls (units of 64 clocks)
-#endif
-__device__ int grid_barrier(uint32_t* sync, int g, int G, int s, int spin_limit) {
-  const int nsub = min(G, PA_NSUB);
-  const int sub = g % nsub;
-  const uint32_t members = uint32_t((G - sub + nsub - 1) / nsub);
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  const uint32_t old = __hip_atomic_fetch_add(&sync[PA_SUB0 + PA_SUBSTRIDE * sub], 1u, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-  if (old + 1u == uint32_t(s + 1) * members) {
-    __builtin_amdgcn_s_waitcnt(0);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  const uint32_t target = uint32_t(s + 1) * uint32_t(nsub);
+// Waits for the tagged partial in *slot; returns its value, or -1 after a
+// give-up (polls exceeded here, or the flag raised elsewhere).
+__device__ double pa_wait(uint64_t* slot, uint64_t tag, uint32_t* sync, int spin_limit) {
   int polls = 0;
-  int ok = 1;
-  while (__hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    if ((polls & 31) == 31 && __hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-      ok = 0;
-      break;
-    }
+  while (true) {
+    const uint64_t b = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (b != PA_EMPTY && (b & PA_SIGN) == tag) return __longlong_as_double(int64_t(b & ~PA_SIGN));
+    if ((polls & 31) == 31 && __hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+      return -1.0;
     if (++polls > spin_limit) {
       __hip_atomic_store(&sync[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      ok = 0;
-      break;
+      return -1.0;
     }
 #if PPD_PA_SLEEP > 0
     __builtin_amdgcn_s_sleep(PPD_PA_SLEEP);
 #endif
   }
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  return ok;
 }
 
 __global__ __launch_bounds__(PA_THREADS) void k_alg2_persistent(PaArgs a) {
+  static_assert(PA_THREADS == 256, "partials are summed over exactly 4 waves");
   __shared__ double red[PA_THREADS / 64][PA_MAXB];
   __shared__ double2 fac[PA_MAXB];
   __shared__ int act[PA_MAXB];
+  __shared__ int quit;
   const int g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int64_t i0 = int64_t(g) * PA_CHUNK;
@@ -247,6 +230,7 @@ __global__ __launch_bounds__(PA_THREADS) void k_alg2_persistent(PaArgs a) {
     fac[tid] = a.bfac[b0 + tid];
     act[tid] = !a.active || a.active[b0 + tid];
   }
+  if (tid == 0) quit = 0;
   __syncthreads();
   for (int s = 0; s < a.steps; ++s) {
     double acc[PA_MAXB];
@@ -276,24 +260,36 @@ __global__ __launch_bounds__(PA_THREADS) void k_alg2_persistent(PaArgs a) {
       if (lane == 0) red[wid][b] = t;
     }
     __syncthreads();
-    double* part = a.part + size_t(s & 1) * size_t(a.G) * PA_MAXB;
-    if (tid == 0) {
-      for (int b = 0; b < nb; ++b)
-        (void)__hip_atomic_exchange(&part[size_t(g) * PA_MAXB + b], ((red[0][b] + red[1][b]) + red[2][b]) + red[3][b],
-                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      (void)grid_barrier(a.sync, g, a.G, s, a.spin_limit);
+    uint64_t* part = a.part + size_t(s & 1) * size_t(a.G) * PA_MAXB;
+    const uint64_t tag = (s & 2) ? PA_SIGN : 0ull;
+    if (wid == 0) {
+      // this wave's earlier exchanges (steps s - 1, s - 2) are acknowledged
+      // before the slot of step s - 2 is overwritten
+      __builtin_amdgcn_s_waitcnt(0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
-    __syncthreads();
+    if (tid < nb) {
+      const double p = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+      // a NaN partial (diverged data) must not read as an empty slot
+      uint64_t bits = uint64_t(__double_as_longlong(p)) & ~PA_SIGN;
+      if (bits == PA_EMPTY) bits |= 1ull;
+      (void)__hip_atomic_exchange(&part[size_t(g) * PA_MAXB + tid], bits | tag, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    }
     // the factors of this workgroup's blocks from all their workgroups' partials
     for (int b = 0; b < nb; ++b) {
       const int j = b0 + b;
       double t = 0.0;
-      for (int gg = a.gfirst[j] + tid; gg <= a.glast[j]; gg += PA_THREADS)
-        t += __hip_atomic_load(&part[size_t(gg) * PA_MAXB + (j - a.wgb0[gg])], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+      int bad = 0;
+      for (int gg = a.gfirst[j] + tid; gg <= a.glast[j]; gg += PA_THREADS) {
+        const double v = pa_wait(&part[size_t(gg) * PA_MAXB + (j - a.wgb0[gg])], tag, a.sync, a.spin_limit);
+        if (v < 0.0) bad = 1;
+        else t += v;
+      }
       t = wave_sum(t);
       __syncthreads();   // red is free again
       if (lane == 0) red[wid][0] = t;
+      if (bad) quit = 1;
       __syncthreads();
       if (tid == 0) {
         const double r = sqrt(((red[0][0] + red[1][0]) + red[2][0]) + red[3][0]), e = a.eps[j];
@@ -301,6 +297,7 @@ __global__ __launch_bounds__(PA_THREADS) void k_alg2_persistent(PaArgs a) {
       }
     }
     __syncthreads();
+    if (quit) break;   // uniform: read after the barrier
   }
 #pragma unroll
   for (int k = 0; k < PA_PER; ++k) {
@@ -310,15 +307,22 @@ __global__ __launch_bounds__(PA_THREADS) void k_alg2_persistent(PaArgs a) {
   // the last step's factors, for the final projection in the gridding:
   // stored by the first workgroup of each block (all others hold the same)
   if (tid < nb && a.gfirst[b0 + tid] == g) a.bfac[b0 + tid] = fac[tid];
-  // the last workgroup out clears the arrival and exit counts for the next launch
+  // the last workgroup out empties every slot for the next launch and clears
+  // the exit count
+  __shared__ int last_out;
   if (tid == 0) {
+    // the partials this wave published are acknowledged before the exit
+    // is counted, so that the reset cannot be overtaken by one of them
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const uint32_t out = __hip_atomic_fetch_add(&a.sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (out == uint32_t(a.G) - 1u) {
-      __hip_atomic_store(&a.sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&a.sync[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      for (int k = 0; k < PA_NSUB; ++k)
-        __hip_atomic_store(&a.sync[PA_SUB0 + PA_SUBSTRIDE * k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    last_out = out == uint32_t(a.G) - 1u;
+  }
+  __syncthreads();
+  if (last_out) {
+    for (size_t e = tid; e < 2 * size_t(a.G) * PA_MAXB; e += PA_THREADS)
+      __hip_atomic_store(&a.part[e], PA_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_store(&a.sync[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_stats(const double* __restrict__ ppart,
     out[6] = s[2];
     out[7] = s[3];
     if (cursor) *cursor += 1;
-    if (flag) out[8 + d] = double(*flag);   // the persistent barrier's give-up flag, read back with them
+    if (flag) out[8 + d] = double(*flag);   // the persistent launch's give-up flag, read back with them
   }
 }
 
@@ -168,7 +168,7 @@ struct IterCtx {
   const uint8_t* basis_active;
   bool sara_forked;   // SARA on the second stream (eager), else the data path (graph)
   bool persistent;    // Algorithm 2 middle steps in one persistent launch
-  int spin_limit;     // its grid-barrier bound (0: default)
+  int spin_limit;     // polls per wait of the persistent launch (0: default)
   hipEvent_t sara_done = nullptr;   // the persistent launch waits for the SARA branch
   // statistics reduced right after the iteration (captured graphs): into
   // stats_out, at the plan's history cursor if stats_cursor
@@ -204,7 +204,7 @@ int data_path(ppd_plan* p, const IterCtx& c) {
       PPD_TRY(block_factors(p, pa));
       // the persistent launch runs with the device to itself: concurrent
       // workgroups of the other branch could take the room some of its
-      // workgroups need while the others wait at the barrier
+      // workgroups need while the others wait for their partials
       if (c.sara_done) PPD_HIP(hipStreamWaitEvent(p->stream, c.sara_done, 0));
       PPD_TRY(alg2_persistent(p, c.dual, c.spin_limit));
       PPD_TRY(grid_dual_factored(p, c.dual));               // last projection, dual finish, gridding
@@ -451,12 +451,12 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
     const double* h = p->host_stats;
     const bool gave_up = h[8 + p->d] != 0.0;
     if (gave_up) {
-      // a grid barrier of the persistent launch gave up waiting (this call
-      // or an earlier one without statistics): its results are not valid
+      // a wait of the persistent launch gave up (this call or an earlier
+      // one without statistics): its results are not valid
       PPD_HIP(hipMemsetAsync(p->pa_sync + 2, 0, sizeof(uint32_t), p->stream));
       PPD_HIP(hipStreamSynchronize(p->stream));
-      return fail(PPD_EDEVICE, "ppd_iterate: a grid barrier of the persistent Algorithm 2 launch gave up "
-                               "waiting; the iterates of this call are not valid");
+      return fail(PPD_EDEVICE, "ppd_iterate: a wait of the persistent Algorithm 2 launch gave up; "
+                               "the iterates of this call are not valid");
     }
     if (stats) {
       stats->iter = st->iter;

@@ -671,6 +671,8 @@ static int create_plan(ppd_plan** out, const ppd_plan_desc* desc, void* stream, 
   {
     const std::vector<uint32_t> zeros(PA_SYNC_WORDS, 0u);
     up(p->pa_sync, zeros.data(), sizeof(uint32_t) * zeros.size());
+    const std::vector<uint64_t> empty(2 * size_t(p->pa_groups) * PA_MAXB, PA_EMPTY);
+    up(p->pa_part, empty.data(), sizeof(uint64_t) * empty.size());
   }
   // the persistent launch needs all its workgroups on the device at once
   if (st == PPD_OK) {

@@ -42,22 +42,15 @@ constexpr int PA_THREADS = 256;   // persistent Algorithm 2: threads per workgro
 #define PPD_PA_PER 12
 #endif
 // points per thread held in registers: 12 (230 VGPRs, 2 waves per SIMD)
-// leaves fewer workgroups to meet at each barrier than 8 and still fits
+// leaves fewer workgroups to wait for at each step than 8 and still fits
 // the co-residency limit at 1.3M points
 constexpr int PA_PER = PPD_PA_PER;
 constexpr int PA_CHUNK = PA_THREADS * PA_PER;
 constexpr int PA_MAXB = 4;        // data blocks one workgroup's points may span
-#ifndef PPD_PA_NSUB
-#define PPD_PA_NSUB 4
-#endif
-// sub-counters of its grid barrier: with 424 workgroups 1, 2, 4, 8, 16 and
-// 32 of them measured 215, 205, 202, 203, 207 and 213 us per iteration
-// with 5 Algorithm 2 steps (one counter takes every arrival; many add a
-// level of contention on the top counter)
-constexpr int PA_NSUB = PPD_PA_NSUB;
-constexpr int PA_SUB0 = 32;       // first sub-counter in the sync array (uint32 index)
-constexpr int PA_SUBSTRIDE = 32;  // one 128-byte line per sub-counter
-constexpr int PA_SYNC_WORDS = PA_SUB0 + PA_SUBSTRIDE * PA_NSUB;
+constexpr int PA_SYNC_WORDS = 32;   // [1] exit count, [2] give-up flag
+// tagged partial slots of the persistent launch (see k_alg2_persistent)
+constexpr uint64_t PA_SIGN = 0x8000000000000000ull;
+constexpr uint64_t PA_EMPTY = 0x7ff8000000000000ull;   // quiet NaN: no partial yet
 #ifndef PPD_FOLD_HEAVY
 #define PPD_FOLD_HEAVY 16
 #endif
@@ -187,8 +180,8 @@ struct ppd_plan {
   int32_t* pa_wgb0 = nullptr;              // [pa_groups] first block of each workgroup
   int32_t* pa_gfirst = nullptr;            // [d] first workgroup of each block
   int32_t* pa_glast = nullptr;             // [d] last workgroup of each block
-  double* pa_part = nullptr;               // [2][pa_groups][PA_MAXB] per-workgroup block partials
-  uint32_t* pa_sync = nullptr;             // [PA_SYNC_WORDS] barrier top count, exits, give-up flag; sub-counters
+  uint64_t* pa_part = nullptr;             // [2][pa_groups][PA_MAXB] tagged per-workgroup block partials
+  uint32_t* pa_sync = nullptr;             // [PA_SYNC_WORDS] exit count, give-up flag
   double* part = nullptr;                  // [2][n_segs] block-norm partials
   double* rpart = nullptr;                 // [n_segs] residual partials
   double* eps_d = nullptr;                 // [d]
@@ -273,7 +266,7 @@ int plain_dual(ppd_plan* p, const DualArgs& a);               // per-block unfus
 int block_factors(ppd_plan* p, const double* part);
 // The n_itr - 1 middle Algorithm 2 steps of the fused form in one persistent
 // launch (needs p->pa_ok and the first step's factors in bfac; leaves the
-// last step's factors in bfac).  spin_limit bounds each grid-barrier wait
+// last step's factors in bfac).  spin_limit bounds each wait
 // (0: default).
 int alg2_persistent(ppd_plan* p, const DualArgs& a, int spin_limit);
 // Maximum co-resident workgroups of the persistent launch on the current

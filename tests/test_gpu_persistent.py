@@ -1,16 +1,16 @@
 """The persistent form of Algorithm 2's middle steps (n_itr > 1, fused
 form): one launch runs the n_itr - 1 middle forward-backward steps of every
-block with the per-point state in registers and a bounded grid barrier per
-step.
+block with the per-point state in registers; each step waits (bounded) for
+the partial norms of its own blocks only.
 
 * At the benchmark's size (512^2, 1.3M points, 16 blocks, n_itr = 5) its
   iterations match the FP64 oracle element by element, eagerly and replayed
   from a graph.
 * It agrees with the launch-pair form (PPD_PERSIST_OFF) on tracks256: the
   same arithmetic with the block norms summed in another order.
-* A barrier whose bounded wait runs out (forced from the host with a spin
-  limit of one poll) releases every workgroup, the kernel ends normally, the
-  call reports PPD_EDEVICE, and the next call runs normally.
+* A wait that runs out (forced from the host with a spin limit of one poll)
+  releases every workgroup, the kernel ends normally, the call reports
+  PPD_EDEVICE, and the next call runs normally.
 """
 import math
 
@@ -84,10 +84,10 @@ def test_persistent_agrees_with_launch_pairs():
     assert rel_err(host(a.z), host(b.z)) < 1e-10
 
 
-def test_barrier_give_up_is_reported_and_recovers():
+def test_wait_give_up_is_reported_and_recovers():
     P = require_gpu()
     import torch
-    announce("persistent barrier give-up (spin limit 1) and recovery")
+    announce("persistent wait give-up (spin limit 1) and recovery")
     inp = synth.make_inputs(synth.WORKLOADS["ppd512"])
     w = inp.workload
     n = w.n
@@ -107,7 +107,7 @@ def test_barrier_give_up_is_reported_and_recovers():
     with pytest.raises(P.PPDError) as err:
         P.ppd_iterate(plan, st, y, U, eps, 1, eta=eta, n_itr=3, spin_limit=1)
     assert err.value.status == P.PPD_EDEVICE and "gave up" in str(err.value)
-    # the flag is cleared and the counters were reset by the last workgroup out
+    # the flag is cleared and the slots were emptied by the last workgroup out
     a, b = P.PPDState(plan, y), P.PPDState(plan, y)
     P.ppd_iterate(plan, a, y, U, eps, 3, eta=eta, n_itr=3)
     P.ppd_iterate(plan, b, y, U, eps, 3, eta=eta, n_itr=3, persistent=P.PERSIST_OFF)
