@@ -328,6 +328,21 @@ typedef struct {
 int ppd_iterate(ppd_plan* plan, ppd_state* state, const ppd_params* params, int n_iter,
                 ppd_stats* stats, double* residual);
 
+/* Algorithm 1 (Sec. 3.2): n_reweights + 1 solves of iters_per_solve
+ * iterations of Algorithm 3 each (as ppd_iterate with params), every solve
+ * warm-started from the state the previous one left.  The first solve uses
+ * params->W (NULL = identity); after solve k < n_reweights the weight
+ * parameter becomes omega^(k+1) = decay^(k+1) omega0 and the re-weights
+ * W = omega / (omega + |Psi^H x|) of the state's image (as ppd_reweight)
+ * are written into W_work, which the next solve uses.  W_work: DEVICE
+ * [9][ny][nx] float32, caller-owned, required when n_reweights > 0 and
+ * not aliasing params->W.  stats: optional HOST [n_reweights + 1], the
+ * statistics of each solve's last iteration (the call then synchronises
+ * after each solve).  omega0 > 0, 0 < decay.  Returns the first error of a
+ * solve or a re-weighting (the state then holds the iterate so far). */
+int ppd_reweighted(ppd_plan* plan, ppd_state* state, const ppd_params* params, int n_reweights,
+                   int iters_per_solve, double omega0, double decay, float* W_work, ppd_stats* stats);
+
 /* ---- differentiable pieces of Algorithm 3 (unrolled iterations) ------- */
 /* One iteration of Algorithm 3 is, in the library's data flow,
  *   g = Theta G F Z x~ (ppd_phi),   (v', z') = dual update (g, v, z),

@@ -507,3 +507,24 @@ extern "C" int ppd_op_norm(ppd_plan* p, const double* U, const float* x0, int ma
   if (iters) *iters = k;
   return PPD_OK;
 }
+
+extern "C" int ppd_reweighted(ppd_plan* p, ppd_state* st, const ppd_params* prm, int n_reweights,
+                              int iters_per_solve, double omega0, double decay, float* W_work, ppd_stats* stats) {
+  if (!p || !st || !prm) return fail(PPD_EINVAL, "ppd_reweighted: NULL argument");
+  if (n_reweights < 0 || iters_per_solve < 1)
+    return fail(PPD_EINVAL, "ppd_reweighted: n_reweights >= 0 and iters_per_solve >= 1 needed");
+  if (!(omega0 > 0.0) || !std::isfinite(omega0) || !(decay > 0.0) || !std::isfinite(decay))
+    return fail(PPD_EINVAL, "ppd_reweighted: omega0 > 0 and decay > 0 needed");
+  if (n_reweights > 0 && (!W_work || W_work == prm->W))
+    return fail(PPD_EINVAL, "ppd_reweighted: W_work is required and must not alias params->W");
+  ppd_params solve = *prm;
+  double omega = omega0;
+  for (int k = 0; k <= n_reweights; ++k) {
+    PPD_TRY(ppd_iterate(p, st, &solve, iters_per_solve, stats ? &stats[k] : nullptr, nullptr));
+    if (k == n_reweights) break;
+    omega *= decay;
+    PPD_TRY(ppd_reweight(p, st->x, float(omega), W_work));
+    solve.W = W_work;
+  }
+  return PPD_OK;
+}

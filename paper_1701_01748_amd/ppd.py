@@ -93,6 +93,8 @@ _PROTOS = {
                               ctypes.POINTER(c_int32)]),
     "ppd_iterate": (c_int32, [c_void_p, ctypes.POINTER(State), ctypes.POINTER(Params), c_int32,
                               ctypes.POINTER(Stats), ctypes.POINTER(c_double)]),
+    "ppd_reweighted": (c_int32, [c_void_p, ctypes.POINTER(State), ctypes.POINTER(Params), c_int32, c_int32,
+                                 c_double, c_double, c_void_p, ctypes.POINTER(Stats)]),
     "ppd_dual_update": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p,
                                   c_void_p, c_int32, c_double, c_double, c_void_p, c_void_p, c_void_p]),
     "ppd_dual_update_vjp": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p,
@@ -650,14 +652,17 @@ def reweighted_ppd(plan: Plan, state: PPDState, y, U, eps, n_reweights: int, ite
     omega <- decay * omega and W = omega / (omega + |Psi^H x|), repeated.
     The first solve uses W = I; the weights of solve k come from solve k-1's
     image with omega^(k) = decay^k omega0.  Returns per-solve statistics."""
-    W = None
-    omega = omega0
-    out = []
-    for k in range(n_reweights + 1):
-        out.append(ppd_iterate(plan, state, y, U, eps, iters_per_solve, W=W, x_true=x_true, **kw))
-        if k < n_reweights:
-            omega *= decay
-            W = ppd_reweight(plan, state.x, omega, W)
+    import torch
+    W = _alloc((9, plan.ny, plan.nx), torch.float32) if n_reweights > 0 else None
+    it = Iteration(plan, state, y, U, eps, x_true=x_true, **kw)
+    st = (Stats * (n_reweights + 1))()
+    it._st.iter = state.iter
+    _check("ppd_reweighted", lib().ppd_reweighted(plan.handle, ctypes.byref(it._st), ctypes.byref(it._prm),
+                                                   int(n_reweights), int(iters_per_solve), float(omega0),
+                                                   float(decay), _ptr(W), st))
+    state.iter = int(it._st.iter)
+    out = [{"iter": int(o.iter), "rel_change": o.rel_change, "x_norm": o.x_norm, "snr_db": o.snr_db,
+            "residual_max": o.residual_max} for o in st]
     return out, W
 
 

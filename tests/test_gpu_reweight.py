@@ -110,3 +110,32 @@ def test_reweighted_loop_snr_parity():
         print(f"[reweight] solve {k}: GPU {s['snr_db']:.3f} dB oracle {h[-1]['snr']:.3f} dB", flush=True)
         assert abs(s["snr_db"] - h[-1]["snr"]) < 0.05, (k, s["snr_db"], h[-1]["snr"])
     assert stats[-1]["snr_db"] > stats[0]["snr_db"]
+
+
+def test_native_outer_loop_matches_the_call_sequence():
+    """ppd_reweighted (Algorithm 1's loop in the library) gives bitwise the
+    iterate of the same calls made one by one: ppd_iterate, then
+    ppd_reweight at omega0 decay^(k+1), then the next solve with W."""
+    P = require_gpu()
+    import torch
+    announce("reweighted loop: native against the call sequence, ppd64")
+    w = synth.WORKLOADS["ppd64"]
+    inp = synth.make_inputs(w)
+    pb = oprob.problem_from_inputs(inp, power_tol=1e-9)
+    plan = P.Plan(64, 64, inp.wu[0], inp.wv[0], inp.block_off)
+    perm = plan.permutation()
+    y = dev(pb.y[perm].astype(np.complex64), torch.complex64)
+    U = dev(pb.U[perm], torch.float64)
+    a, b = P.PPDState(plan, y), P.PPDState(plan, y)
+    stats, Wa = P.reweighted_ppd(plan, a, y, U, pb.eps, 2, 20, omega0=1e-2, decay=0.25, eta=pb.eta, mu=1.0)
+    Wb, omega = None, 1e-2
+    for k in range(3):
+        P.ppd_iterate(plan, b, y, U, pb.eps, 20, W=Wb, eta=pb.eta, mu=1.0)
+        if k < 2:
+            omega *= 0.25
+            Wb = P.ppd_reweight(plan, b.x, omega, Wb)
+    torch.cuda.synchronize()
+    assert a.iter == b.iter == 60 and len(stats) == 3
+    for k in ("x", "xt", "v", "u", "z"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    assert torch.equal(Wa, Wb)
