@@ -379,7 +379,8 @@ def cpu_baseline(inp, iters: int) -> dict:
     sparse products split by rows over a thread pool and scipy.fft running
     on the same number of threads (at most the 16 cores a one-GPU machine
     shares); plus per-operator medians and the 64x64 workload's 200
-    iterations end to end."""
+    iterations end to end, and the 256^2 tracks workload's per-iteration
+    median (n_itr = 5) with its 500-iteration run estimated from it."""
     import numpy as np
 
     import synth
@@ -441,6 +442,20 @@ def cpu_baseline(inp, iters: int) -> dict:
     t1 = time.perf_counter()
     O.iterate(pb64.op, pb64.y, pb64.U, pb64.eps, pb64.block_off, O.Params(eta=1e-3), s64, 200)
     ops["ppd64_200_iterations_s"] = round(time.perf_counter() - t1, 3)
+    # the 256^2 tracks workload (4 blocks, n_itr = 5 as in its PD / PPD
+    # comparison): median of 5 iterations, and that times its 500 iterations
+    w256 = synth.WORKLOADS["tracks256"]
+    i256 = synth.make_inputs(w256)
+    pb256 = oprob.problem_from_inputs(i256, with_eta=False)
+    s256 = O.init_state(w256.n, w256.n, pb256.y)
+    p256 = O.Params(eta=1e-3, mu=1.0 / pb256.U.max(), n_itr=5)
+
+    def one256():
+        O.iterate(pb256.op, pb256.y, pb256.U, pb256.eps, pb256.block_off, p256, s256, 1)
+
+    it256 = median_ms(one256, reps=5)
+    ops["tracks256_iteration_ms"] = it256
+    ops["tracks256_500_iterations_s_estimate"] = round(500 * it256 / 1e3, 1)
     return {"value": round(iters / dt, 5), "unit": "PPD iterations/s", "cores": workers, "kind": "oracle",
             "host_cpus": os.cpu_count(), "per_operator": ops,
             "sample": f"{iters} full FP64 oracle iterations of {w.name} (setup excluded), {dt:.1f} s; sparse "
