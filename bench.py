@@ -300,8 +300,8 @@ def main():
 
     if not args.quick:
         # ---- Phi / Phi^H visibilities per second (plan order) ------------------------
-        def time_calls(fn, reps=30):
-            for _ in range(3):
+        def time_calls(fn, reps=100):
+            for _ in range(10):
                 fn()
             ts = []
             for _ in range(reps):
