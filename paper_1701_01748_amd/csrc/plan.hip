@@ -214,7 +214,7 @@ static int dalloc(ppd_plan* p, T** ptr, size_t count) {
 static void destroy_plan(ppd_plan* p) {
   if (!p) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < ppd::GRAPH_SLOTS; ++k) {
     if (p->graph_exec[k]) (void)hipGraphExecDestroy(p->graph_exec[k]);
     if (p->graph[k]) (void)hipGraphDestroy(p->graph[k]);
   }
@@ -727,7 +727,7 @@ int ppd_plan_destroy(ppd_plan* plan) {
 
 int ppd_plan_set_stream(ppd_plan* plan, void* stream) {
   if (!plan) return fail(PPD_EINVAL, "NULL plan");
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < ppd::GRAPH_SLOTS; ++k) {
     if (plan->graph_exec[k]) (void)hipGraphExecDestroy(plan->graph_exec[k]);
     if (plan->graph[k]) (void)hipGraphDestroy(plan->graph[k]);
     plan->graph_exec[k] = nullptr;

@@ -68,6 +68,15 @@ constexpr int FOLD_HEAVY = PPD_FOLD_HEAVY;   // item regions above which a tile'
 #endif
 // Product steps of the matrix-core gridding whose LDS operands are read
 // before the first of their products (2, 4 or 8).
+// Captured-iteration graphs per plan: one iteration without statistics
+// partials, one with them and the periodic reduction, one with the partials
+// only, and a captured run (a statistics period, or GRAPH_RUN iterations
+// without partials).
+constexpr int GRAPH_SLOTS = 4;
+#ifndef PPD_GRAPH_RUN
+#define PPD_GRAPH_RUN 8
+#endif
+constexpr int GRAPH_RUN = PPD_GRAPH_RUN;
 #ifndef PPD_GRIDM_READ_AHEAD
 #define PPD_GRIDM_READ_AHEAD 2
 #endif
@@ -213,9 +222,9 @@ struct ppd_plan {
 
   // graph replay of one iteration: slot 0 without the statistics partials,
   // slot 1 with them and the periodic reduction, slot 2 with them only
-  hipGraphExec_t graph_exec[3] = {nullptr, nullptr, nullptr};
-  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
-  std::string graph_key[3];
+  hipGraphExec_t graph_exec[ppd::GRAPH_SLOTS] = {};
+  hipGraph_t graph[ppd::GRAPH_SLOTS] = {};
+  std::string graph_key[ppd::GRAPH_SLOTS];
 
   // optional per-launch timing
   bool timing = false;
