@@ -338,8 +338,11 @@ int ppd_iterate(ppd_plan* plan, ppd_state* state, const ppd_params* params, int 
  * [9][ny][nx] float32, caller-owned, required when n_reweights > 0 and
  * not aliasing params->W.  stats: optional HOST [n_reweights + 1], the
  * statistics of each solve's last iteration (the call then synchronises
- * after each solve).  omega0 > 0, 0 < decay.  Returns the first error of a
- * solve or a re-weighting (the state then holds the iterate so far). */
+ * after each solve); params->stats_history, if given, ends with the rows of
+ * the last solve (each solve is one ppd_iterate call).  omega0 > 0,
+ * 0 < decay; omega is passed to the re-weighting in float32 and must stay
+ * > 0 there.  Returns the first error of a solve or a re-weighting (the
+ * state then holds the iterate so far). */
 int ppd_reweighted(ppd_plan* plan, ppd_state* state, const ppd_params* params, int n_reweights,
                    int iters_per_solve, double omega0, double decay, float* W_work, ppd_stats* stats);
 
