@@ -432,8 +432,8 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
       // Each graph launch costs a few microseconds of the device's time, so
       // iterations are replayed in captured runs: with periodic statistics,
       // a period of `every` iterations whose last one reduces them (slot 3);
-      // without, runs of GRAPH_RUN iterations without partials (slot 3); the
-      // rest one at a time (slots 0-2).  Measured at 512^2: 143.9 us per
+      // otherwise runs of GRAPH_RUN iterations without partials (slot 3);
+      // the rest one at a time (slots 0-2).  Measured at 512^2: 143.9 us per
       // iteration replayed one at a time, 137.9 in periods of 10, 137.0
       // eager.
       int t = 0;
@@ -445,8 +445,11 @@ extern "C" int ppd_iterate(ppd_plan* p, ppd_state* st, const ppd_params* prm, in
           t += every;
           continue;
         }
-        const int last_plain = n_iter - ((stats || residual) ? 1 : 0);
-        if (every == 0 && GRAPH_RUN > 1 && t + GRAPH_RUN <= last_plain) {
+        // iterations [t, plain_end) need neither the periodic reduction nor
+        // the final read-back
+        const int next_periodic = every > 0 ? (t / every + 1) * every - 1 : n_iter;
+        const int plain_end = std::min(next_periodic, n_iter - ((stats || residual) ? 1 : 0));
+        if (GRAPH_RUN > 1 && t + GRAPH_RUN <= plain_end) {
           PPD_TRY(iteration_graph(p, c0, GRAPH_RUN, nullptr, 3, &ex));
           PPD_HIP(hipGraphLaunch(ex, p->stream));
           t += GRAPH_RUN;
