@@ -404,18 +404,32 @@ static_assert(ST / 2 + FILT_STRIDE / 2 + 1 <= WIN && WIN <= ST, "the LL window f
 static_assert(WIN / 2 + FILT_STRIDE / 2 <= SK, "the inner coefficient window fits the staging");
 
 // Level 1 for all 8 wavelet bases, plus the Dirac part, times 1/3, on a
-// STF x STF output tile.  The coefficient windows of all 8 bases are staged
-// in one pass (one round of global loads), then the row passes of all bases,
-// then the column passes, which each thread sums over the bases in registers.
+// STF x STF output tile.  The coefficient windows of all 8 bases are loaded
+// in one pass (one round of global loads, into registers), then staged in
+// LDS FPARTS bases at a time: the row passes of a part, then its column
+// passes, which each thread sums over the bases in registers in basis
+// order.  Parts keep the workgroup's LDS small, which leaves room on each
+// compute unit for the concurrent data-path launches.
+#ifndef PPD_FINAL_PARTS
+#define PPD_FINAL_PARTS 2
+#endif
+constexpr int FPARTS = PPD_FINAL_PARTS;
+constexpr int FB = 8 / FPARTS;                       // bases per part
+static_assert(FB * FPARTS == 8, "the parts split the 8 bases evenly");
 constexpr int FINAL_THREADS = 128;
 constexpr int FH = STF / 2;                          // coefficients per tile side and band
 constexpr int FKS = FH + FILT_STRIDE / 2;            // staged row stride (FH + max Q)
-constexpr int FROWS = 8 * FH + 36;                   // sum over Q = 1..8 of (FH + Q)
 constexpr int FELEM = 8 * FH * FH + 2 * FH * 36 + 204;   // sum over Q of (FH + Q)^2
 constexpr int FEPT = (FELEM + FINAL_THREADS - 1) / FINAL_THREADS;
+constexpr int FROWS = FB * FH + FB * (17 - FB) / 2;  // rows of the last (largest) part: sum of FH + Q over it
+constexpr int FPART = FROWS * FKS;                   // staging index offset of one part
 static_assert(FH * STF == FINAL_THREADS, "one column pair per thread");
 
-__device__ __forceinline__ int final_row0(int q) { return (q - 1) * FH + (q - 1) * q / 2; }
+// first staged row of basis q within its part (each part from row 0)
+__device__ __forceinline__ int final_row0(int q) {
+  const int q0 = (q - 1) / FB * FB + 1;
+  return (q - q0) * FH + ((q - 1) * q - (q0 - 1) * q0) / 2;
+}
 __device__ __forceinline__ int final_elem0(int q) {
   int e = 0;
   for (int p = 1; p < q; ++p) e += (FH + p) * (FH + p);
@@ -467,12 +481,47 @@ __device__ __forceinline__ void final_cols(const float* __restrict__ filt, const
   }
 }
 
+template <int Q, int QE>
+__device__ __forceinline__ void final_rows_range(const float* __restrict__ filt, const float* s_c, float* s_a,
+                                                 float* s_d) {
+  final_rows<Q>(filt, s_c, s_a, s_d);
+  if constexpr (Q < QE) final_rows_range<Q + 1, QE>(filt, s_c, s_a, s_d);
+}
+
+template <int Q, int QE>
+__device__ __forceinline__ void final_cols_range(const float* __restrict__ filt, const float* s_a,
+                                                 const float* s_d, int j, int m, float& o0, float& o1) {
+  final_cols<Q>(filt, s_a, s_d, j, m, o0, o1);
+  if constexpr (Q < QE) final_cols_range<Q + 1, QE>(filt, s_a, s_d, j, m, o0, o1);
+}
+
+// Part PART of the bases: stage its windows (s_c was last read by the
+// previous part's row passes, before the barrier ahead of its column
+// passes), then its row and column passes.
+template <int PART>
+__device__ __forceinline__ void final_part(const float* __restrict__ filt, float* s_c, float* s_a, float* s_d,
+                                           const float (&vals)[FEPT][4], const int (&at)[FEPT], int j, int m,
+                                           float& o0, float& o1) {
+#pragma unroll
+  for (int k = 0; k < FEPT; ++k) {
+    if (at[k] >= PART * FPART && at[k] < (PART + 1) * FPART) {
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) s_c[c4 * FPART + at[k] - PART * FPART] = vals[k][c4];
+    }
+  }
+  __syncthreads();
+  final_rows_range<PART * FB + 1, PART * FB + FB>(filt, s_c, s_a, s_d);
+  __syncthreads();
+  final_cols_range<PART * FB + 1, PART * FB + FB>(filt, s_a, s_d, j, m, o0, o1);
+  if constexpr (PART + 1 < FPARTS) final_part<PART + 1>(filt, s_c, s_a, s_d, vals, at, j, m, o0, o1);
+}
+
 __global__ __launch_bounds__(FINAL_THREADS) void k_idwt_final(const float* __restrict__ u,
                                                               const float* __restrict__ rec,
                                                               const float* __restrict__ filt,
                                                               const float* __restrict__ W, SaraGeom g,
                                                               float* __restrict__ out) {
-  __shared__ float s_c[4 * FROWS * FKS];
+  __shared__ float s_c[4 * FPART];   // one part's LL, LH, HL, HH windows
   __shared__ float s_a[FROWS * STF], s_d[FROWS * STF];
   const int nx = g.nx, ww = g.nx, hh = g.ny;
   const int oh = hh >> 1, ow = ww >> 1;
@@ -507,38 +556,14 @@ __global__ __launch_bounds__(FINAL_THREADS) void k_idwt_final(const float* __res
       vals[k][1] = ucoef[plh] * (wcoef ? wcoef[plh] : 1.0f);
       vals[k][2] = ucoef[phl] * (wcoef ? wcoef[phl] : 1.0f);
       vals[k][3] = ucoef[phh] * (wcoef ? wcoef[phh] : 1.0f);
-      at[k] = (final_row0(q) + a) * FKS + b;
+      at[k] = (final_row0(q) + a) * FKS + b + (q - 1) / FB * FPART;
     }
   }
   const int j = tid / STF, m = tid - j * STF;
   const size_t P0 = size_t(y0 + 2 * j) * nx + (x0 + m), P1 = P0 + nx;
   const float dirac0 = u[P0] * (W ? W[P0] : 1.0f), dirac1 = u[P1] * (W ? W[P1] : 1.0f);
-#pragma unroll
-  for (int k = 0; k < FEPT; ++k) {
-    if (at[k] >= 0) {
-#pragma unroll
-      for (int c4 = 0; c4 < 4; ++c4) s_c[c4 * FROWS * FKS + at[k]] = vals[k][c4];
-    }
-  }
-  __syncthreads();
-  final_rows<1>(filt, s_c, s_a, s_d);
-  final_rows<2>(filt, s_c, s_a, s_d);
-  final_rows<3>(filt, s_c, s_a, s_d);
-  final_rows<4>(filt, s_c, s_a, s_d);
-  final_rows<5>(filt, s_c, s_a, s_d);
-  final_rows<6>(filt, s_c, s_a, s_d);
-  final_rows<7>(filt, s_c, s_a, s_d);
-  final_rows<8>(filt, s_c, s_a, s_d);
-  __syncthreads();
   float o0 = 0.f, o1 = 0.f;
-  final_cols<1>(filt, s_a, s_d, j, m, o0, o1);
-  final_cols<2>(filt, s_a, s_d, j, m, o0, o1);
-  final_cols<3>(filt, s_a, s_d, j, m, o0, o1);
-  final_cols<4>(filt, s_a, s_d, j, m, o0, o1);
-  final_cols<5>(filt, s_a, s_d, j, m, o0, o1);
-  final_cols<6>(filt, s_a, s_d, j, m, o0, o1);
-  final_cols<7>(filt, s_a, s_d, j, m, o0, o1);
-  final_cols<8>(filt, s_a, s_d, j, m, o0, o1);
+  final_part<0>(filt, s_c, s_a, s_d, vals, at, j, m, o0, o1);
   const float third = 1.0f / 3.0f;
   out[P0] = (o0 + dirac0) * third;
   out[P1] = (o1 + dirac1) * third;
