@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PPD iters/s + Phi/Phi^T vis/s at 512^2, M=1.3M; batched vs plain, HBM GB/s"
 PREHEAT_S = 0.15   # minimum length of the untimed warm-up phase (seconds)
+PREHEAT_CALL = 10  # iterations per call of that phase
 HBM_PEAK_GBS = 8000.0
 CRITICAL_PATH = ("fft_rows_fwd", "fft_cols_fwd", "degrid", "grid", "fold", "fft_cols_inv", "fft_rows_inv")
 # kernel kind -> source file that defines it (traffic figures are only used
@@ -211,7 +212,7 @@ def main():
     # reduced on the device during the call into a history, as a stopping
     # test would, and the call ends by reading back the last ones.
     every = max(1, args.stats_every)
-    rows = max(args.steps, args.warmup) // every
+    rows = max(args.steps, args.warmup, PREHEAT_CALL) // every
     hist = torch.zeros(rows * (8 + len(off) - 1), dtype=torch.float64, device="cuda")
 
     def timed(graph: bool):
@@ -230,8 +231,8 @@ def main():
         # warm-up phase has lasted PREHEAT_S; their count is reported.
         extra = 0
         while time.perf_counter() - t_w < PREHEAT_S:
-            it.run(10, stats=False)
-            extra += 10
+            it.run(PREHEAT_CALL, stats=False)
+            extra += PREHEAT_CALL
             torch.cuda.synchronize()
         preheat[graph] = extra
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

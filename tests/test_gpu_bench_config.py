@@ -152,3 +152,25 @@ def test_ppd512_precision_report():
     lines = [f"{name:42s} {rel:10.2e} {peak:10.2e}" for name, rel, peak in rows]
     print("[precision] ppd512, error against the FP64 oracle (relative norm, peak-relative):\n" +
           "\n".join(lines), flush=True)
+
+
+def test_bench_line_with_fewer_steps_than_the_statistics_period():
+    """bench.py's one JSON line, in a child process, for a run shorter than
+    the statistics period and than one call of the untimed warm-up phase
+    (3 timed steps, 1 warm-up step): the keys of the line's contract and a
+    positive value."""
+    import subprocess
+    import sys
+    announce("bench.py --steps 3 --warmup 1")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--steps", "3", "--warmup", "1", "--quick",
+                        "--no-cpu-baseline"], capture_output=True, text=True, timeout=300, cwd=root)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    assert len(lines) == 1, r.stdout[-2000:]
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline"):
+        assert k in d, k
+    assert d["steps"] == 3 and d["warmup"] == 1 and d["n_gpus"] == 1
+    assert d["value"] > 0 and d["config"]["workload"] == "ppd512"
