@@ -66,8 +66,6 @@ constexpr int FOLD_HEAVY = PPD_FOLD_HEAVY;   // item regions above which a tile'
 #ifndef PPD_GRIDM_WPG
 #define PPD_GRIDM_WPG 1
 #endif
-// Product steps of the matrix-core gridding whose LDS operands are read
-// before the first of their products (2, 4 or 8).
 // Captured-iteration graphs per plan: one iteration without statistics
 // partials, one with them and the periodic reduction, one with the partials
 // only, and a captured run (a statistics period, or GRAPH_RUN iterations
@@ -77,6 +75,8 @@ constexpr int GRAPH_SLOTS = 4;
 #define PPD_GRAPH_RUN 8
 #endif
 constexpr int GRAPH_RUN = PPD_GRAPH_RUN;
+// Product steps of the matrix-core gridding whose LDS operands are read
+// before the first of their products (2, 4 or 8).
 #ifndef PPD_GRIDM_READ_AHEAD
 #define PPD_GRIDM_READ_AHEAD 2
 #endif
