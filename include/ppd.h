@@ -272,10 +272,12 @@ typedef struct {
                                       once (about 1.5M visibilities) and no
                                       3072 consecutive plan-order points
                                       span more than 4 blocks (the launch
-                                      waits for the SARA branch of its
-                                      iteration and needs the device to
-                                      itself: work that other streams run
-                                      beside it can make a wait give up);
+                                      runs beside the SARA branch of its
+                                      iteration, whose launches never wait
+                                      on it; work that other streams run
+                                      beside it and that waits itself, such
+                                      as another plan's persistent launch,
+                                      can make a wait give up);
                                       PPD_PERSIST_OFF (1): one launch pair
                                       per step                               */
   int32_t spin_limit;              /* polls of one wait of the persistent

@@ -169,7 +169,6 @@ struct IterCtx {
   bool sara_forked;   // SARA on the second stream (eager), else the data path (graph)
   bool persistent;    // Algorithm 2 middle steps in one persistent launch
   int spin_limit;     // polls per wait of the persistent launch (0: default)
-  hipEvent_t sara_done = nullptr;   // the persistent launch waits for the SARA branch
   // statistics reduced right after the iteration (captured graphs): into
   // stats_out, at the plan's history cursor if stats_cursor
   double* stats_out = nullptr;
@@ -200,12 +199,11 @@ int data_path(ppd_plan* p, const IterCtx& c) {
     PPD_TRY(degrid_dual(p, c.dual, pa));                    // dual argument, first Alg. 2 step
     if (c.dual.n_itr > 1 && c.persistent) {
       // the middle steps in one launch, state in registers; it leaves the
-      // last step's factors for the gridding
+      // last step's factors for the gridding.  It runs beside the SARA
+      // branch: workgroups of it that the SARA launches keep from being
+      // resident at first get room as those finish (they never wait on
+      // this launch), while the resident ones wait for their partials.
       PPD_TRY(block_factors(p, pa));
-      // the persistent launch runs with the device to itself: concurrent
-      // workgroups of the other branch could take the room some of its
-      // workgroups need while the others wait for their partials
-      if (c.sara_done) PPD_HIP(hipStreamWaitEvent(p->stream, c.sara_done, 0));
       PPD_TRY(alg2_persistent(p, c.dual, c.spin_limit));
       PPD_TRY(grid_dual_factored(p, c.dual));               // last projection, dual finish, gridding
     } else {
@@ -238,22 +236,16 @@ int sara_path(ppd_plan* p, const IterCtx& c) {
 // into a graph, the data path is forked: replayed graphs put a forked SARA
 // branch's join, and with it the primal update, on the other hardware queue
 // (measured 163 against 155 us per iteration).
-//
-// With the persistent Algorithm 2 launch (n_itr > 1) SARA is forked in both
-// modes and the persistent launch waits for it (it is done by then: it runs
-// beside the forward FFT and the degridding).
 int one_iteration(ppd_plan* p, const IterCtx& c) {
   PPD_HIP(hipEventRecord(p->ev_fork, p->stream));
   PPD_HIP(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
-  if (c.sara_forked || c.persistent) {
+  if (c.sara_forked) {
     {
       OnStream on(p, p->aux);
       PPD_TRY(sara_path(p, c));
       PPD_HIP(hipEventRecord(p->ev_join, p->aux));
     }
-    IterCtx cd = c;
-    if (c.persistent) cd.sara_done = p->ev_join;
-    PPD_TRY(data_path(p, cd));
+    PPD_TRY(data_path(p, c));
   } else {
     {
       OnStream on(p, p->aux);
