@@ -21,12 +21,15 @@ def _problem(seed=51, n=64, M=8000, d=4):
     return pb, wu, wv
 
 
-@pytest.mark.parametrize("graph,prox,tile", [(False, "fb", 0), (True, "fb", 0), (False, "exact", 0),
-                                             (True, "fb", 8), (False, "exact", 8)])
-def test_randomised_iterations_match_oracle(graph, prox, tile):
+@pytest.mark.parametrize("graph,prox,tile,n_itr", [(False, "fb", 0, 2), (True, "fb", 0, 2), (False, "exact", 0, 2),
+                                                   (True, "fb", 8, 2), (False, "exact", 8, 2),
+                                                   (False, "fb", 8, 4), (True, "fb", 8, 4)])
+def test_randomised_iterations_match_oracle(graph, prox, tile, n_itr):
+    """With n_itr = 4 the middle Algorithm 2 steps run in the persistent
+    launch, whose inactive blocks keep their z through every step."""
     P = require_gpu()
     import torch
-    announce(f"randomised iterations graph={graph} prox={prox} tile={tile}")
+    announce(f"randomised iterations graph={graph} prox={prox} tile={tile} n_itr={n_itr}")
     pb, wu, wv = _problem()
     n, d = pb.x_true.shape[0], len(pb.eps)
     T = 8
@@ -38,13 +41,15 @@ def test_randomised_iterations_match_oracle(graph, prox, tile):
         y = dev(pb.y[perm].astype(np.complex64), torch.complex64)
         U = dev(pb.U[perm], torch.float64)
         st = P.PPDState(plan, y)
-        kw = dict(eta=pb.eta, mu=1.0, n_itr=2, use_graph=graph)
+        if n_itr > 2:
+            assert plan.info.persistent == 1
+        kw = dict(eta=pb.eta, mu=1.0, n_itr=n_itr, use_graph=graph)
         if prox == "exact":
             kw.update(prox=P.PROX_EXACT, n_newton=16)
         P.randomised_ppd(plan, st, y, U, pb.eps, bm, pm, **kw)
         stream.synchronize()
     ost = O.init_state(n, n, pb.y)
-    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, O.Params(eta=pb.eta, mu=1.0, n_itr=2, prox=prox), ost, T,
+    O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, O.Params(eta=pb.eta, mu=1.0, n_itr=n_itr, prox=prox), ost, T,
               active=list(zip(bm, pm)))
     assert_op_close(host(st.x), ost.x, what="x")
     assert_op_close(host(st.v), ost.v[perm], what="v")
