@@ -11,6 +11,10 @@ the partial norms of its own blocks only.
 * A wait that runs out (forced from the host with a spin limit of one poll)
   releases every workgroup, the kernel ends normally, the call reports
   PPD_EDEVICE, and the next call runs normally.
+* Small uneven blocks: workgroups spanning 4 blocks (the most one may
+  span) match the oracle; a plan with 3072 consecutive points over 5
+  blocks reports no persistent launch and runs launch pairs, which match
+  the oracle too.
 """
 import math
 
@@ -112,3 +116,36 @@ def test_wait_give_up_is_reported_and_recovers():
     P.ppd_iterate(plan, a, y, U, eps, 3, eta=eta, n_itr=3)
     P.ppd_iterate(plan, b, y, U, eps, 3, eta=eta, n_itr=3, persistent=P.PERSIST_OFF)
     assert rel_err(host(a.x), host(b.x)) < 1e-6
+
+
+@pytest.mark.parametrize("M,d,seed,persistent", [(10000, 8, 73, 1), (16000, 12, 74, 0)])
+def test_blocks_per_workgroup_edges(M, d, seed, persistent):
+    P = require_gpu()
+    import torch
+    announce(f"persistent edges M={M} d={d} seed={seed}")
+    n = 64
+    x, wu, wv, off = synth.small_case(n, M, seed=seed, d=d)
+    # blocks spanned by each run of 3072 consecutive points (blocks are contiguous in plan order)
+    spans = [int(np.sum((off[:-1] < min((g + 1) * 3072, M)) & (off[1:] > g * 3072)))
+             for g in range((M + 3071) // 3072)]
+    assert max(spans) == (4 if persistent else 5)
+    pb = oprob.make_problem(x, wu, wv, off, synth.noise_unit(M, 400 + seed), 30.0, np.ones((n, n)),
+                            power_tol=1e-8)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = P.Plan(n, n, wu, wv, off, stream=stream)
+        assert plan.info.persistent == persistent
+        perm = plan.permutation()
+        y = dev(pb.y[perm].astype(np.complex64), torch.complex64)
+        U = dev(pb.U[perm], torch.float64)
+        st = P.PPDState(plan, y)
+        ost = O.init_state(n, n, pb.y)
+        prm = O.Params(eta=pb.eta, mu=1.0, n_itr=5)
+        for graph in (False, True):
+            O.iterate(pb.op, pb.y, pb.U, pb.eps, pb.block_off, prm, ost, 3)
+            P.ppd_iterate(plan, st, y, U, pb.eps, 3, eta=pb.eta, mu=1.0, n_itr=5, use_graph=graph)
+            stream.synchronize()
+            mode = "graph" if graph else "eager"
+            assert_op_close(host(st.x), ost.x, what=f"x ({mode})")
+            assert_op_close(host(st.v), ost.v[perm], what=f"v ({mode})")
+            assert_op_close(host(st.z), ost.z[perm], what=f"z ({mode})")
