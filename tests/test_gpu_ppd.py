@@ -217,3 +217,36 @@ def test_periodic_statistics_history(graph):
     assert np.array_equal(got, np.array(ref)), (got, np.array(ref))
     assert s2["iter"] == 6 and s2["rel_change"] == ref[-1][0]
     assert np.array_equal(host(st2.x), host(st.x))
+
+
+@pytest.mark.parametrize("n_iter,every", [(37, 10), (21, 0), (30, 25)])
+def test_replayed_schedules_match_eager(n_iter, every):
+    """Calls whose replay mixes captured statistics periods, runs of 8
+    iterations without statistics and single iterations (37 iterations with
+    statistics every 10, 21 without periodic statistics, 30 with statistics
+    every 25): the iterates and the statistics history agree bit for bit
+    with eager launches."""
+    P = require_gpu()
+    import torch
+    announce(f"replayed schedule n_iter={n_iter} every={every}")
+    pb, wu, wv = _small_problem(seed=17)
+    n = pb.x_true.shape[0]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = P.Plan(n, n, wu, wv, pb.block_off, stream=stream)
+        perm, y, U = _gpu_inputs(P, plan, pb)
+        xt = dev(pb.x_true.astype(np.float32), torch.float32)
+        rows = max(1, n_iter // every) if every else 1
+        out = {}
+        for graph in (False, True):
+            st = P.PPDState(plan, y)
+            hist = torch.zeros(rows * (8 + plan.d), dtype=torch.float64, device="cuda")
+            kw = dict(stats_every=every, stats_history=hist) if every else {}
+            s = P.ppd_iterate(plan, st, y, U, pb.eps, n_iter, eta=pb.eta, x_true=xt, use_graph=graph, **kw)
+            stream.synchronize()
+            out[graph] = (s, {k: host(getattr(st, k)) for k in ("x", "xt", "v", "u", "z")}, host(hist))
+    (se, ae, he), (sg, ag, hg) = out[False], out[True]
+    for k in ae:
+        assert np.array_equal(ag[k], ae[k]), k
+    assert np.array_equal(hg, he)
+    assert sg["iter"] == se["iter"] == n_iter and sg["rel_change"] == se["rel_change"]
