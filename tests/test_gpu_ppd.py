@@ -219,21 +219,23 @@ def test_periodic_statistics_history(graph):
     assert np.array_equal(host(st2.x), host(st.x))
 
 
-@pytest.mark.parametrize("n_iter,every", [(37, 10), (21, 0), (30, 25)])
-def test_replayed_schedules_match_eager(n_iter, every):
+@pytest.mark.parametrize("n_iter,every,n_itr", [(37, 10, 1), (21, 0, 1), (30, 25, 1), (25, 10, 4)])
+def test_replayed_schedules_match_eager(n_iter, every, n_itr):
     """Calls whose replay mixes captured statistics periods, runs of 8
     iterations without statistics and single iterations (37 iterations with
     statistics every 10, 21 without periodic statistics, 30 with statistics
-    every 25): the iterates and the statistics history agree bit for bit
-    with eager launches."""
+    every 25, and 25 with the persistent Algorithm 2 launch of n_itr = 4):
+    the iterates and the statistics history agree bit for bit with eager
+    launches."""
     P = require_gpu()
     import torch
-    announce(f"replayed schedule n_iter={n_iter} every={every}")
+    announce(f"replayed schedule n_iter={n_iter} every={every} n_itr={n_itr}")
     pb, wu, wv = _small_problem(seed=17)
     n = pb.x_true.shape[0]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         plan = P.Plan(n, n, wu, wv, pb.block_off, stream=stream)
+        assert n_itr == 1 or plan.info.persistent == 1
         perm, y, U = _gpu_inputs(P, plan, pb)
         xt = dev(pb.x_true.astype(np.float32), torch.float32)
         rows = max(1, n_iter // every) if every else 1
@@ -242,7 +244,8 @@ def test_replayed_schedules_match_eager(n_iter, every):
             st = P.PPDState(plan, y)
             hist = torch.zeros(rows * (8 + plan.d), dtype=torch.float64, device="cuda")
             kw = dict(stats_every=every, stats_history=hist) if every else {}
-            s = P.ppd_iterate(plan, st, y, U, pb.eps, n_iter, eta=pb.eta, x_true=xt, use_graph=graph, **kw)
+            s = P.ppd_iterate(plan, st, y, U, pb.eps, n_iter, eta=pb.eta, x_true=xt, use_graph=graph,
+                              n_itr=n_itr, **kw)
             stream.synchronize()
             out[graph] = (s, {k: host(getattr(st, k)) for k in ("x", "xt", "v", "u", "z")}, host(hist))
     (se, ae, he), (sg, ag, hg) = out[False], out[True]
