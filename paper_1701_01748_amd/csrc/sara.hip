@@ -3,7 +3,7 @@
 // the Mallat layout of the image.  Float32.
 //
 // Analysis runs one launch per level for the 8 wavelet bases at once
-// (blockIdx.z = basis; the Dirac basis rides in the first launch): a
+// (one grid dimension per basis; the Dirac basis rides in the first launch): a
 // workgroup stages the periodic input region of its output tile in LDS,
 // filters the columns, then the rows, and writes the four sub-bands.  In
 // the dual mode (the sparsity dual update of Algorithm 3) every final coefficient c is
@@ -33,6 +33,20 @@ struct SaraGeom {
 __device__ __host__ inline size_t lvl_size(const SaraGeom& g, int l) { return g.N >> (2 * l); }
 
 enum { A_PLAIN = 0, A_DUAL = 1 };
+
+// The tile (x, y) and basis (z) of this workgroup.  Consecutive workgroups
+// go round-robin to the XCDs; the tiles are handed out so that each XCD
+// takes a contiguous band of them instead, and neighbouring tiles, whose
+// staged windows overlap, meet in one L2.
+struct TileId {
+  int x, y, z;
+};
+__device__ inline TileId sara_tile() {
+  const int gx = gridDim.x, gy = gridDim.y, total = gx * gy * int(gridDim.z);
+  int lin = int(blockIdx.x) + gx * (int(blockIdx.y) + gy * int(blockIdx.z));
+  if (total % MAX_XCD == 0) lin = xcd_remap(lin, total);
+  return TileId{lin % gx, (lin / gx) % gy, lin / (gx * gy)};
+}
 
 // Filters of db-Q: 2Q taps each, low-pass h and high-pass g, in registers
 // (the addresses are wave-uniform, so the compiler uses scalar loads).
@@ -138,8 +152,8 @@ __device__ void dwt_tile(const float* __restrict__ src, int sstride, float scale
 
 static_assert(AT * AT <= 256, "an analysis tile must fit one output per thread of 256");
 
-// Level l of the 8 wavelet bases (blockIdx.z = basis - 1); at level 1 the
-// Dirac basis is blockIdx.z = 8.  `active` (dual mode, may be NULL) masks
+// Level l of the 8 wavelet bases (tile z = basis - 1); at level 1 the
+// Dirac basis is z = 8.  `active` (dual mode, may be NULL) masks
 // the bases updated this iteration.  Level 1 reads the image scaled by 1/3,
 // deeper levels the low-pass band of the previous level.
 template <int MODE>
@@ -153,8 +167,9 @@ __global__ __launch_bounds__(256) void k_dwt(const float* __restrict__ x, float*
   const int hh = g.ny >> (l - 1), ww = g.nx >> (l - 1);
   const int oh = hh >> 1, ow = ww >> 1;
   const int toy = min(AT, oh), tox = min(AT, ow);
-  const int k0y = blockIdx.y * toy, k0x = blockIdx.x * tox;
-  const int q = blockIdx.z + 1;   // 1..8 wavelets, 9 = Dirac (level 1 only)
+  const TileId tl = sara_tile();
+  const int k0y = tl.y * toy, k0x = tl.x * tox;
+  const int q = tl.z + 1;   // 1..8 wavelets, 9 = Dirac (level 1 only)
   const float third = 1.0f / 3.0f;
   // randomised updates (Algorithm 3 with a random set of bases): an inactive basis keeps
   // its u_i (basis index 0 is the Dirac basis)
@@ -323,8 +338,9 @@ __global__ __launch_bounds__(256) void k_idwt(const float* __restrict__ u, float
   __shared__ float s_a[SK * ST], s_d[SK * ST];
   const int hh = g.ny >> (l - 1), ww = g.nx >> (l - 1);
   const int tsy = min(ST, hh), tsx = min(ST, ww);
-  const int y0 = blockIdx.y * tsy, x0 = blockIdx.x * tsx;
-  const int q = blockIdx.z + 1;
+  const TileId tl = sara_tile();
+  const int y0 = tl.y * tsy, x0 = tl.x * tsx;
+  const int q = tl.z + 1;
   const float* ucoef = u + size_t(q) * g.N;
   const float* wcoef = W ? W + size_t(q) * g.N : nullptr;
   const float* llsrc;
@@ -384,8 +400,9 @@ __global__ __launch_bounds__(256) void k_idwt2(const float* __restrict__ u, floa
   const int l = g.L - 1;                                      // outer level
   const int hh = g.ny >> (l - 1), ww = g.nx >> (l - 1);
   const int tsy = min(ST, hh), tsx = min(ST, ww);
-  const int y0 = blockIdx.y * tsy, x0 = blockIdx.x * tsx;
-  const int q = blockIdx.z + 1;
+  const TileId tl = sara_tile();
+  const int y0 = tl.y * tsy, x0 = tl.x * tsx;
+  const int q = tl.z + 1;
   const float* ucoef = u + size_t(q) * g.N;
   const float* wcoef = W ? W + size_t(q) * g.N : nullptr;
   float* dst = rec + g.off[l - 1] + size_t(q - 1) * lvl_size(g, l - 1);
@@ -525,7 +542,8 @@ __global__ __launch_bounds__(FINAL_THREADS) void k_idwt_final(const float* __res
   __shared__ float s_a[FROWS * STF], s_d[FROWS * STF];
   const int nx = g.nx, ww = g.nx, hh = g.ny;
   const int oh = hh >> 1, ow = ww >> 1;
-  const int y0 = blockIdx.y * STF, x0 = blockIdx.x * STF;
+  const TileId tl = sara_tile();
+  const int y0 = tl.y * STF, x0 = tl.x * STF;
   const int tid = threadIdx.x;
   // stage: element e of the flattened (basis, row, column) windows
   float vals[FEPT][4];
