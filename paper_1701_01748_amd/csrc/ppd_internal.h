@@ -55,10 +55,11 @@ constexpr uint64_t PA_EMPTY = 0x7ff8000000000000ull;   // quiet NaN: no partial 
 #define PPD_FOLD_HEAVY 16
 #endif
 constexpr int FOLD_HEAVY = PPD_FOLD_HEAVY;   // item regions above which a tile's fold takes a whole workgroup
-// Work items per workgroup of the 8 x 8 degridding with the dual update and
-// of the matrix-core gridding (runs of consecutive items, one wave each).
+// Work items per workgroup of the 8 x 8 degridding with the dual update
+// (runs of consecutive items, one wave each; 1 measured ahead of 2 once the
+// SARA branch took less of the device).
 #ifndef PPD_DEGRID_RUN
-#define PPD_DEGRID_RUN 2
+#define PPD_DEGRID_RUN 1
 #endif
 #ifndef PPD_GRIDM_RUN
 #define PPD_GRIDM_RUN 2
