@@ -78,7 +78,7 @@ def measured_traffic(kind: str, workload: str, tile: int, chunk: int):
 
 
 # kernel kind -> the kernel's name in a rocprofv3 summary (fused iteration, 8 x 8 tiles)
-KIND_KERNEL = {"degrid": "k_degrid8", "grid": "k_grid_mfma<true>", "fold": "k_fold8",
+KIND_KERNEL = {"degrid": "k_degrid<8, true>", "grid": "k_grid_mfma<true>", "fold": "k_fold8",
                "fft_rows_fwd": "k_fft_rows_fwd", "fft_cols_fwd": "k_fft_cols_fwd", "fft_cols_inv": "k_fft_cols_inv",
                "fft_rows_inv": "k_fft_rows_inv<true, true>"}
 

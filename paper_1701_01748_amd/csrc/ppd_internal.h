@@ -55,11 +55,12 @@ constexpr uint64_t PA_EMPTY = 0x7ff8000000000000ull;   // quiet NaN: no partial 
 #define PPD_FOLD_HEAVY 16
 #endif
 constexpr int FOLD_HEAVY = PPD_FOLD_HEAVY;   // item regions above which a tile's fold takes a whole workgroup
-// Work items per workgroup of the 8 x 8 degridding with the dual update
-// (runs of consecutive items, one wave each; 1 measured ahead of 2 once the
-// SARA branch took less of the device).
+// Work items per workgroup of the 8 x 8 degridding with the dual update:
+// 0 takes one item per single-wave workgroup in k_degrid<8, DUAL> (88
+// VGPRs, 5 waves per SIMD), n > 0 runs of n items in k_degrid8 (107 VGPRs,
+// 4 waves per SIMD), which the lighter SARA branch no longer repays.
 #ifndef PPD_DEGRID_RUN
-#define PPD_DEGRID_RUN 1
+#define PPD_DEGRID_RUN 0
 #endif
 #ifndef PPD_GRIDM_RUN
 #define PPD_GRIDM_RUN 2
